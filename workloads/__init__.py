@@ -1,0 +1,171 @@
+"""Seeded synthetic inputs for the lattice MVM / CG workloads.
+
+This module only draws random numbers: it holds none of the lattice
+arithmetic, so both the CPU oracle's tests and the GPU path's tests and
+benchmark can take their inputs from here without sharing any method code.
+
+The five workloads mirror the shapes of the paper's regression benchmarks
+(Section 5, the lattice-size table: n from ~1.6e4 to ~2e6, d from 3 to 20),
+which are not available here; every array is synthetic:
+
+  ws1  n=2,000     d=3   X ~ N(0, I), l = 1, C = 1, noise 0.1, tol 1e-4
+  ws2  n=500,000   d=8   mixture of 20 Gaussians, l ~ logU[0.5, 2], C = 1,
+                         noise 0.05, tol 1e-2
+  ws3  n=2,000,000 d=11  mixture of 50 Gaussians, l ~ logU[0.5, 2],
+                         C = 16 (1 target ~ N(0,1) + 15 Rademacher probes),
+                         noise 0.05, 20 fixed CG iterations
+  ws4  n=1,000,000 d=16  X ~ U[-1, 1]^16, l ~ logU[0.3, 3], C = 8 ~ N(0,1)
+  ws5  serving stream: 256 requests, n ~ logU[1e3, 3e5], d ~ U{3..20},
+                         mixture of 20, l ~ logU[0.5, 2], C = 8, noise 0.05,
+                         tol 1e-4, 1,000 test points each, Poisson arrivals
+
+Every generator takes an explicit seed; the defaults are 1000 + workload id.
+X is fp32 (row-major n x d), lengthscales fp64 (host constants), values fp32.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+__all__ = [
+    "mixture", "Workload", "ws1", "ws2", "ws3", "ws4", "ws5_requests",
+    "small_case", "by_name",
+]
+
+
+def mixture(rng: np.random.Generator, n: int, d: int, k: int,
+            spread: float = 2.0, std: float = 0.5) -> np.ndarray:
+    """Equal-weight Gaussian mixture, standardised per dimension, as fp32.
+
+    Component means ~ N(0, spread^2 I) (spread 2 gives covariance 4I),
+    each point = its component mean + std * N(0, I); the result is centred
+    and scaled to unit variance per column in fp64, then rounded to fp32.
+    """
+    means = rng.normal(0.0, spread, size=(k, d))
+    comp = rng.integers(0, k, size=n)
+    x = means[comp] + std * rng.standard_normal((n, d))
+    mu = x.mean(axis=0)
+    sd = x.std(axis=0)
+    sd[sd == 0] = 1.0
+    return ((x - mu) / sd).astype(np.float32)
+
+
+def log_uniform(rng: np.random.Generator, lo: float, hi: float, size) -> np.ndarray:
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size=size))
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    X: np.ndarray            # (n, d) fp32
+    lengthscales: np.ndarray  # (d,) fp64
+    values: np.ndarray       # (n, C) fp32
+    noise: float
+    tol: float
+    max_iter: int
+    outputscale: float = 1.0
+    order: int = 1
+
+    @property
+    def n(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def d(self) -> int:
+        return int(self.X.shape[1])
+
+    @property
+    def C(self) -> int:
+        return int(self.values.shape[1])
+
+
+def ws1(seed: int = 1001, n: int = 2000) -> Workload:
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, 3)).astype(np.float32)
+    ell = np.ones(3)
+    V = rng.standard_normal((n, 1)).astype(np.float32)
+    return Workload("ws1", X, ell, V, noise=0.1, tol=1e-4, max_iter=500)
+
+
+def ws2(seed: int = 1002, n: int = 500_000) -> Workload:
+    rng = np.random.default_rng(seed)
+    X = mixture(rng, n, 8, 20)
+    ell = log_uniform(rng, 0.5, 2.0, 8)
+    V = rng.standard_normal((n, 1)).astype(np.float32)
+    return Workload("ws2", X, ell, V, noise=0.05, tol=1e-2, max_iter=500)
+
+
+def ws3(seed: int = 1003, n: int = 2_000_000, channels: int = 16) -> Workload:
+    rng = np.random.default_rng(seed)
+    X = mixture(rng, n, 11, 50)
+    ell = log_uniform(rng, 0.5, 2.0, 11)
+    y = rng.standard_normal((n, 1))
+    probes = rng.integers(0, 2, size=(n, channels - 1)) * 2.0 - 1.0
+    V = np.concatenate([y, probes], axis=1).astype(np.float32)
+    return Workload("ws3", X, ell, V, noise=0.05, tol=0.0, max_iter=20)
+
+
+def ws4(seed: int = 1004, n: int = 1_000_000) -> Workload:
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1.0, 1.0, size=(n, 16)).astype(np.float32)
+    ell = log_uniform(rng, 0.3, 3.0, 16)
+    V = rng.standard_normal((n, 8)).astype(np.float32)
+    return Workload("ws4", X, ell, V, noise=0.05, tol=1e-4, max_iter=500)
+
+
+def small_case(seed: int, n: int, d: int, channels: int = 1, kind: str = "normal",
+               ell_range=(0.5, 2.0)) -> Workload:
+    """A small generic case for parity and property tests."""
+    rng = np.random.default_rng(seed)
+    if kind == "normal":
+        X = rng.standard_normal((n, d)).astype(np.float32)
+    elif kind == "mixture":
+        X = mixture(rng, n, d, 5)
+    elif kind == "uniform":
+        X = rng.uniform(-1.0, 1.0, size=(n, d)).astype(np.float32)
+    else:
+        raise ValueError(kind)
+    ell = log_uniform(rng, ell_range[0], ell_range[1], d)
+    V = rng.standard_normal((n, channels)).astype(np.float32)
+    return Workload(f"small-{kind}-{n}x{d}", X, ell, V, noise=0.1, tol=1e-4,
+                    max_iter=500)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival_s: float        # arrival time relative to the stream start
+    X: np.ndarray           # (n, d) fp32 training inputs
+    X_test: np.ndarray      # (n_test, d) fp32 prediction inputs
+    lengthscales: np.ndarray
+    values: np.ndarray      # (n, C) fp32: target + probes
+    noise: float
+    tol: float
+
+
+def ws5_requests(seed: int = 1005, count: int = 256, mean_gap_s: float = 0.01,
+                 n_lo: int = 1000, n_hi: int = 300_000, d_lo: int = 3, d_hi: int = 20,
+                 channels: int = 8, n_test: int = 1000) -> list:
+    """Serving stream: Poisson arrivals with the given mean gap (1/lambda).
+
+    Training and test inputs of one request come from one mixture draw, so
+    the test points lie where the training data does.
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(mean_gap_s, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(count):
+        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        d = int(rng.integers(d_lo, d_hi + 1))
+        Xall = mixture(rng, n + n_test, d, 20)
+        ell = log_uniform(rng, 0.5, 2.0, d)
+        y = rng.standard_normal((n, 1))
+        probes = rng.integers(0, 2, size=(n, channels - 1)) * 2.0 - 1.0
+        V = np.concatenate([y, probes], axis=1).astype(np.float32)
+        out.append(Request(i, float(t[i]), Xall[:n], Xall[n:], ell, V, 0.05, 1e-4))
+    return out
+
+
+def by_name(name: str, **kw) -> Workload:
+    return {"ws1": ws1, "ws2": ws2, "ws3": ws3, "ws4": ws4}[name](**kw)
