@@ -1,0 +1,180 @@
+"""Benchmark of the lattice MVM inside CG on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input: build the
+lattice of X (elevation, simplex, hash insert, numbering, neighbours), then
+20 iterations of batched CG on 16 right-hand-side columns (1 target + 15
+Rademacher probes), each iteration one fused multi-column splat/blur/slice
+plus the CG vector updates. Inputs are resident in HBM before timing.
+
+value = n * C * (MVMs per step) / step time   [points*channels/s]
+
+Printed as one JSON line, with a roofline entry for the dominant kernel
+(algorithmic bytes per launch over its HIP-event-measured mean duration) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, cg: bool) -> float:
+    """Algorithmic HBM bytes of ONE launch of a kernel kind (fp32 values,
+    int32 indices; every array touched once per launch)."""
+    D, T = d + 1, 2 * r
+    chains = 2 if sym else 1
+    if kind == "splat":   # idx + w, V in, U out
+        return n * D * 8 + n * C * 4 + m * C * 4
+    if kind == "slice":   # idx + w, U (both chains) in, out (+ p in CG)
+        return n * D * 8 + chains * m * C * 4 + n * C * 4 + (n * C * 4 if cg else 0)
+    if kind == "blur":    # per chain: U in, U out, neighbour lists
+        return chains * (2 * m * C * 4 + T * m * 4)
+    if kind == "cg_update":  # x, p, q, r in; x, r out
+        return 6 * n * C * 4
+    if kind == "cg_dir":     # r, p in; p out
+        return 3 * n * C * 4
+    if kind == "cg_init":    # b in; x, r, p out
+        return 4 * n * C * 4
+    if kind == "fill":
+        return m * C * 4
+    return 0.0
+
+
+def mvm_bytes(n, d, m, C, r, sym, cg=False):
+    return (kernel_bytes("splat", n, d, m, C, r, sym, cg) + (d + 1) * kernel_bytes("blur", n, d, m, C, r, sym, cg)
+            + kernel_bytes("slice", n, d, m, C, r, sym, cg))
+
+
+def cpu_baseline(w, n_sample: int, iters: int):
+    """The oracle as it stands: build + per-column CG on the first n_sample
+    points, single-threaded."""
+    import oracle
+    Xs, Vs = w.X[:n_sample], w.values[:n_sample].astype(np.float64)
+    t0 = time.perf_counter()
+    olat = oracle.Lattice(Xs, w.lengthscales)
+    olat.cg(Vs, w.noise, 0.0, max_iter=iters)
+    dt = time.perf_counter() - t0
+    C = w.values.shape[1]
+    return {"value": n_sample * C * iters / dt, "unit": "points*ch/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample} of {w.n} points, all {C} columns: oracle build + {iters} "
+                      f"CG iterations per column (fp64, single thread), {dt:.2f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--blur", default="symmetric", choices=["symmetric", "forward"])
+    ap.add_argument("--cpu-sample", type=int, default=200_000,
+                    help="points in the oracle's CPU-baseline sample (0 = skip)")
+    ap.add_argument("--mvm-reps", type=int, default=20, help="extra timed lattice_mvm calls")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2106_06695_amd as sgp
+    import workloads
+
+    torch.cuda.set_device(0)
+    w = workloads.ws3()
+    n, d, C = w.n, w.d, w.C
+    X = torch.from_numpy(w.X).cuda()
+    V = torch.from_numpy(w.values).cuda()
+    x = torch.empty_like(V)
+    iters = w.max_iter
+    sym = args.blur == "symmetric"
+
+    def step():
+        lat = sgp.lattice_build(X, w.lengthscales, blur=args.blur)
+        sgp.cg_solve(lat, V, w.noise, 0.0, max_iter=iters, x=x)
+        m = lat.m
+        lat.free()
+        return m
+
+    for _ in range(args.warmup):
+        m = step()
+    torch.cuda.synchronize()
+    with sgp.profile() as prof:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            m = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n * C * iters / (ms_per_step / 1e3)
+
+    # per-kernel event timings over the timed region
+    kernels = {}
+    for kind, (launches, ms) in prof.results.items():
+        if launches:
+            b = kernel_bytes(kind, n, d, m, C, 1, sym, cg=True)
+            avg = ms / launches
+            kernels[kind] = {"launches": launches, "total_ms": round(ms, 3), "avg_us": round(avg * 1e3, 2),
+                             "algo_GBps": round(b / (avg / 1e3) / 1e9, 1) if b else None}
+    mvm_kinds = [k for k in ("splat", "blur", "slice") if k in kernels]
+    dom = max(mvm_kinds, key=lambda k: kernels[k]["total_ms"])
+    dom_bytes = kernel_bytes(dom, n, d, m, C, 1, sym, cg=True)
+    dom_avg_s = kernels[dom]["total_ms"] / kernels[dom]["launches"] / 1e3
+    achieved = dom_bytes / dom_avg_s / 1e9
+
+    # standalone MVMs on a resident lattice (outside the timed steps)
+    lat = sgp.lattice_build(X, w.lengthscales, blur=args.blur)
+    out = torch.empty_like(V)
+    for _ in range(3):
+        sgp.lattice_mvm(lat, V, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.mvm_reps):
+        sgp.lattice_mvm(lat, V, out)
+    torch.cuda.synchronize()
+    mvm_s = (time.perf_counter() - t0) / args.mvm_reps
+    B = mvm_bytes(n, d, lat.m, C, 1, sym)
+    lat.free()
+
+    line = {
+        "metric": "lattice MVM points*ch/s at n=2M d=11 (build + 20 batched CG iterations per step)",
+        "value": value,
+        "unit": "points*ch/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ws3: n=2,000,000 d=11 X from a 50-component Gaussian mixture "
+                               "(standardised), lengthscales logU[0.5,2], C=16 (1 target + 15 "
+                               "Rademacher probes), noise 0.05, RBF r=1, " + args.blur + " blur, 20 CG iterations",
+                   "n": n, "d": d, "C": C, "m": m, "m_over_L": m / (n * (d + 1)),
+                   "cg_iterations": iters, "blur": args.blur},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algo_bytes_per_launch": dom_bytes},
+        "mvm_only": {"ms": mvm_s * 1e3, "points_ch_per_s": n * C / mvm_s,
+                     "algo_bytes": B, "algo_GBps": B / mvm_s / 1e9,
+                     "frac_of_hbm_peak": B / mvm_s / 1e9 / HBM_PEAK_GBS},
+        "kernels": kernels,
+    }
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n), iters)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,152 @@
+/* simplexgp.h — C ABI of the MI355X permutohedral-lattice kernel library.
+ *
+ * The library computes the Simplex-GP kernel operator of Kapoor, Finzi, Wang
+ * and Wilson, "SKIing on Simplices: Kernel Interpolation on the
+ * Permutohedral Lattice for Scalable Gaussian Processes" (ICML 2021,
+ * arXiv:2106.06695):
+ *
+ *     K ~= W_X K_UU W_X^T      (Section 4, eq. ski_to_bf)
+ *
+ * where W_X^T is the splat of point values onto the vertices of their
+ * enclosing simplices with barycentric weights, K_UU is the blur along the
+ * d+1 lattice directions with a stencil sampled from the kernel, and W_X is
+ * the slice back to the points (Section 3.2, paragraphs Splat, Blur and
+ * Slice), and conjugate-gradient solves with K + noise*I that use only such
+ * matrix-vector products (Section 2, Krylov methods).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers unless marked "host". They are
+ *     owned by the caller, dense and row-major (the last index is
+ *     contiguous). The library never frees or retains them beyond the call,
+ *     except that a lattice keeps its own copies of what it needs (it does
+ *     not keep X).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Work is
+ *     ordered on that stream. lattice_mvm is fully asynchronous; calls that
+ *     return host values (lattice_build, cg_solve, lattice_export)
+ *     synchronise the stream before returning.
+ *   - Every call returns an SGP_* status. On failure sgp_last_error() gives
+ *     a message (thread-local; valid until the next failing call on the
+ *     same thread). Argument checks run on the host before any GPU work, so
+ *     SGP_EINVAL from them leaves the device untouched.
+ *   - A lattice handle holds work buffers that lattice_mvm and cg_solve
+ *     reuse: calls on ONE handle must not overlap in time (use one stream
+ *     per handle, or order them). Different handles are independent.
+ */
+#ifndef SIMPLEXGP_H
+#define SIMPLEXGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgp_lattice sgp_lattice; /* opaque; owned by the library */
+
+enum sgp_status {
+  SGP_OK = 0,
+  SGP_EINVAL = -1,    /* bad argument, or non-finite values in X */
+  SGP_ENOMEM = -2,    /* device or host allocation failed */
+  SGP_EOVERFLOW = -3, /* a lattice coordinate leaves int32 (|x|/l too large) */
+  SGP_EHIP = -4,      /* HIP runtime error */
+  SGP_EHASH = -5      /* lattice hash table failed to verify after retries */
+};
+
+/* Blur order over the d+1 lattice directions (Section 3.2, Blur). The
+ * directions are applied one after another over a fixed point set; on a
+ * truncated lattice the result depends on the order:
+ *   FORWARD   directions 0, 1, ..., d   (the paper's sequential blur)
+ *   REVERSE   directions d, ..., 1, 0   (the transpose of FORWARD)
+ *   SYMMETRIC (FORWARD + REVERSE) / 2   (exactly symmetric; default) */
+enum sgp_blur { SGP_BLUR_SYMMETRIC = 0, SGP_BLUR_FORWARD = 1, SGP_BLUR_REVERSE = 2 };
+
+/* Stationary kernel whose samples k(t s), t = -r..r, form the blur stencil;
+ * the spacing s balances spatial and spectral coverage (Section 4.1,
+ * eq. balance_coverage). */
+enum sgp_kernel { SGP_KERNEL_RBF = 0, SGP_KERNEL_MATERN32 = 1 };
+
+typedef struct sgp_opts {
+  int32_t order;     /* stencil half-width r, 1..8 (default 1, the paper's setting) */
+  int32_t kernel;    /* enum sgp_kernel (default SGP_KERNEL_RBF) */
+  int32_t blur;      /* enum sgp_blur (default SGP_BLUR_SYMMETRIC) */
+  float outputscale; /* sigma_f^2 multiplying the whole operator (default 1) */
+  float load_factor; /* hash table fill bound relative to n(d+1), in (0, 0.9] (default 0.5) */
+} sgp_opts;
+
+/* Fill *o with the defaults above (host). */
+void sgp_opts_default(sgp_opts* o);
+
+/* Build the lattice of the points X (n x d, fp32) with per-dimension
+ * lengthscales (host, d doubles, each finite and > 0). Computes the
+ * enclosing simplex and barycentric weights of every point (Section 3.2,
+ * Splat), inserts every vertex into a GPU hash table, numbers the m
+ * distinct lattice points by first occurrence in the (point, vertex) scan,
+ * and tabulates the neighbours of each lattice point along each direction
+ * (Section 3.2, Blur).
+ * Limits: n >= 1, 1 <= d <= 32, n*(d+1) <= 2^30.
+ * Errors: SGP_EINVAL (arguments, NaN/Inf in X), SGP_EOVERFLOW (|x_j|/l_j so
+ * large that a lattice coordinate leaves int32), SGP_ENOMEM, SGP_EHIP,
+ * SGP_EHASH. On success *out receives a handle to free with lattice_free.
+ * Synchronises `stream` (the lattice size m is read back). */
+int lattice_build(const float* X, int64_t n, int32_t d, const double* lengthscales,
+                  const sgp_opts* opts /* host; NULL = defaults */, void* stream,
+                  sgp_lattice** out);
+
+/* out = outputscale * W_X K_UU W_X^T values, per column (eq. ski_to_bf).
+ * values, out: n x C fp32, C >= 1; out must not overlap values.
+ * Asynchronous on `stream`. */
+int lattice_mvm(const sgp_lattice* L, const float* values, int32_t C, float* out, void* stream);
+
+/* Conjugate gradients on (outputscale*K + noise*I) x = rhs, each of the C
+ * columns an independent recurrence from x0 = 0 (Section 2, Krylov methods;
+ * Section 5.4 for the tolerance semantics). A column stops when its
+ * recursive residual ||r||/||rhs|| <= tol, or after max_iter iterations;
+ * tol = 0 runs exactly max_iter iterations. Non-convergence is not an error.
+ * rhs, x: n x C fp32 device arrays, 1 <= C <= 64, x must not overlap rhs.
+ * iters, rel_residual: host arrays of C entries (or NULL) receiving the
+ * iterations taken and the final recursive relative residual.
+ * noise >= 0, tol >= 0, max_iter >= 1. Synchronises `stream` before it
+ * returns (it polls convergence every few iterations). */
+int cg_solve(const sgp_lattice* L, const float* rhs, int32_t C, float noise, float tol,
+             int32_t max_iter, float* x, int32_t* iters /* host */,
+             float* rel_residual /* host */, void* stream);
+
+/* Sizes of a built lattice (host outputs, any may be NULL): n, d, the
+ * number m of lattice points (m <= n(d+1), Section 5.2) and the device
+ * bytes the handle holds. */
+int lattice_info(const sgp_lattice* L, int64_t* n, int32_t* d, int64_t* m,
+                 int64_t* device_bytes);
+
+/* Copy the lattice structure to HOST arrays (any may be NULL):
+ *   keys m x d      int32  first d coordinates of each lattice point
+ *                          (the last is minus their sum)
+ *   idx  n x (d+1)  int32  lattice point of vertex k of point i's simplex
+ *   w    n x (d+1)  fp32   barycentric weight of that vertex
+ *   nbr  m x (d+1) x 2r int32  neighbour of point j along direction k at
+ *                          offsets t = -r..-1, 1..r; -1 where absent.
+ * Synchronous. */
+int lattice_export(const sgp_lattice* L, int32_t* keys, int32_t* idx, float* w, int32_t* nbr);
+
+/* Release a lattice and its device memory (NULL is a no-op). Waits for the
+ * device to finish work that may still use it. */
+void lattice_free(sgp_lattice* L);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* sgp_last_error(void);
+
+/* Kernel timing with HIP events, for benchmarks. While enabled, every
+ * kernel launch of the library is bracketed by two events on its stream.
+ * sgp_profile_read synchronises the recorded events and reports, for one
+ * kernel kind, the number of launches and their summed duration in ms
+ * since the last reset. Kinds are numbered 0..sgp_profile_kinds()-1. */
+int sgp_profile_enable(int on);
+int sgp_profile_reset(void);
+int sgp_profile_kinds(void);
+const char* sgp_profile_name(int kind);
+int sgp_profile_read(int kind, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIMPLEXGP_H */

@@ -1,0 +1,217 @@
+"""Python binding of libsimplexgp (the MI355X permutohedral-lattice library).
+
+Argument marshalling only: every step of the lattice build, MVM and CG runs
+in the library's HIP kernels. Tensors are torch CUDA (ROCm) tensors, used
+here for device memory and streams; the functions mirror the C ABI in
+include/simplexgp.h:
+
+    lattice_build(X, lengthscales, ...) -> Lattice
+    lattice_mvm(lat, values, out=None)  -> out = outputscale * W K_UU W^T values
+    cg_solve(lat, rhs, noise, tol, max_iter=500, x=None) -> (x, iters, rel_residual)
+    lattice_info(lat), lattice_export(lat), lattice_free(lat)
+
+If the compiled library is missing, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+
+__all__ = [
+    "SGPError", "Lattice", "lattice_build", "lattice_mvm", "cg_solve", "lattice_info",
+    "lattice_export", "lattice_free", "profile", "library_path",
+]
+
+SYMMETRIC, FORWARD, REVERSE = 0, 1, 2
+RBF, MATERN32 = 0, 1
+_BLUR = {"symmetric": SYMMETRIC, "forward": FORWARD, "reverse": REVERSE}
+_KERNEL = {"rbf": RBF, "matern32": MATERN32}
+
+
+class SGPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SGPError(rc, _lib.load().sgp_last_error().decode())
+
+
+def _stream(dev=None):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dev_f32(t, name: str, rows: Optional[int] = None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if rows is not None and (t.dim() not in (1, 2) or t.shape[0] != rows):
+        raise ValueError(f"{name} must have {rows} rows")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _cols(t) -> int:
+    return 1 if t.dim() == 1 else int(t.shape[1])
+
+
+class Lattice:
+    """Handle of a lattice built on the device (owned by the library)."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, d: int, order: int, blur: int,
+                 kernel: int, outputscale: float, device):
+        self._h = handle
+        self.n, self.d, self.order = n, d, order
+        self.blur, self.kernel, self.outputscale = blur, kernel, outputscale
+        self.device = device
+        m = ctypes.c_int64()
+        _check(_lib.load().lattice_info(self._h, None, None, ctypes.byref(m), None))
+        self.m = int(m.value)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            _lib.load().lattice_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("lattice already freed")
+        return self._h
+
+    def mvm(self, values, out=None):
+        return lattice_mvm(self, values, out)
+
+    def cg(self, rhs, noise: float, tol: float, max_iter: int = 500, x=None):
+        return cg_solve(self, rhs, noise, tol, max_iter, x)
+
+
+def lattice_build(X, lengthscales: Sequence[float], order: int = 1, kernel: str = "rbf",
+                  blur: str = "symmetric", outputscale: float = 1.0,
+                  load_factor: float = 0.5) -> Lattice:
+    """Build the lattice of X (n x d fp32 CUDA tensor); see lattice_build in
+    include/simplexgp.h (Section 3.2 of the paper: Splat and Blur)."""
+    lib = _lib.load()
+    if X.dim() != 2:
+        raise ValueError("X must be n x d")
+    n, d = int(X.shape[0]), int(X.shape[1])
+    px = _dev_f32(X, "X")
+    ell = np.ascontiguousarray(np.asarray(lengthscales, dtype=np.float64).reshape(-1))
+    if ell.shape[0] != d:
+        raise ValueError("lengthscales must have d entries")
+    opts = _lib.Opts()
+    lib.sgp_opts_default(ctypes.byref(opts))
+    opts.order = int(order)
+    opts.kernel = _KERNEL[kernel]
+    opts.blur = _BLUR[blur]
+    opts.outputscale = float(outputscale)
+    opts.load_factor = float(load_factor)
+    h = ctypes.c_void_p()
+    _check(lib.lattice_build(px, n, d, ell.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
+                             _stream(X.device), ctypes.byref(h)))
+    return Lattice(h, n, d, int(order), opts.blur, opts.kernel, float(outputscale), X.device)
+
+
+def lattice_mvm(lat: Lattice, values, out=None):
+    """out = outputscale * W K_UU W^T values (eq. ski_to_bf), asynchronous."""
+    import torch
+    pv = _dev_f32(values, "values", lat.n)
+    C = _cols(values)
+    if out is None:
+        out = torch.empty_like(values)
+    po = _dev_f32(out, "out", lat.n)
+    if out.shape != values.shape:
+        raise ValueError("out must have the shape of values")
+    _check(_lib.load().lattice_mvm(lat.handle, pv, C, po, _stream(values.device)))
+    return out
+
+
+def cg_solve(lat: Lattice, rhs, noise: float, tol: float, max_iter: int = 500, x=None):
+    """Solve (outputscale*K + noise*I) x = rhs per column by CG (Section 2).
+    Returns (x, iterations per column, recursive relative residual per column)."""
+    import torch
+    pb = _dev_f32(rhs, "rhs", lat.n)
+    C = _cols(rhs)
+    if x is None:
+        x = torch.empty_like(rhs)
+    px = _dev_f32(x, "x", lat.n)
+    iters = np.zeros(C, dtype=np.int32)
+    rel = np.zeros(C, dtype=np.float32)
+    _check(_lib.load().cg_solve(lat.handle, pb, C, float(noise), float(tol), int(max_iter), px,
+                                iters.ctypes.data_as(ctypes.c_void_p),
+                                rel.ctypes.data_as(ctypes.c_void_p), _stream(rhs.device)))
+    return x, iters, rel
+
+
+def lattice_info(lat: Lattice) -> dict:
+    n, d, m, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.load().lattice_info(lat.handle, ctypes.byref(n), ctypes.byref(d), ctypes.byref(m),
+                                    ctypes.byref(b)))
+    return {"n": n.value, "d": d.value, "m": m.value, "device_bytes": b.value}
+
+
+def lattice_export(lat: Lattice):
+    """Host copies of keys (m x d), idx (n x d+1), w (n x d+1), nbr (m x d+1 x 2r)."""
+    D, T = lat.d + 1, 2 * lat.order
+    keys = np.zeros((lat.m, lat.d), dtype=np.int32)
+    idx = np.zeros((lat.n, D), dtype=np.int32)
+    w = np.zeros((lat.n, D), dtype=np.float32)
+    nbr = np.zeros((lat.m, D, T), dtype=np.int32)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(_lib.load().lattice_export(lat.handle, P(keys), P(idx), P(w), P(nbr)))
+    return keys, idx, w, nbr
+
+
+def lattice_free(lat: Lattice):
+    lat.free()
+
+
+class profile:
+    """Context manager: per-kernel HIP-event timings of library launches.
+
+    with profile() as prof: ...;  prof.results -> {kind: (launches, total_ms)}
+    """
+
+    def __enter__(self):
+        lib = _lib.load()
+        _check(lib.sgp_profile_reset())
+        _check(lib.sgp_profile_enable(1))
+        self.results = {}
+        return self
+
+    def __exit__(self, *exc):
+        lib = _lib.load()
+        _check(lib.sgp_profile_enable(0))
+        self.results = read_profile()
+        return False
+
+
+def read_profile() -> dict:
+    lib = _lib.load()
+    out = {}
+    for k in range(lib.sgp_profile_kinds()):
+        launches, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(lib.sgp_profile_read(k, ctypes.byref(launches), ctypes.byref(ms)))
+        out[lib.sgp_profile_name(k).decode()] = (int(launches.value), float(ms.value))
+    return out

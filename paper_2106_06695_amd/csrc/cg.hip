@@ -1,0 +1,273 @@
+// Conjugate gradients on (outputscale*K + noise*I) x = b, one independent
+// recurrence per column (Section 2, Krylov methods; Section 5.4 on
+// tolerances). All scalars stay on the device: the slice of each MVM emits
+// per-block partial sums of p.q, a one-block kernel turns them into alpha,
+// the update kernel moves x and r and emits partial sums of r.r, and a
+// second one-block kernel decides convergence and beta. The host only polls
+// the per-column "active" flags every few iterations.
+//
+// Partial sums are reduced in a fixed order in fp64, so a run is
+// reproducible given the MVM's own rounding.
+#include <cmath>
+#include <cstring>
+
+#include "sgp_internal.h"
+
+namespace sgp {
+namespace {
+
+struct CgState {
+  double rr[kMaxCgCols];
+  double bnorm[kMaxCgCols];
+  double alpha[kMaxCgCols];
+  double beta[kMaxCgCols];
+  float rel[kMaxCgCols];
+  int32_t active[kMaxCgCols];
+  int32_t iters[kMaxCgCols];
+};
+
+enum ScalarMode { SM_START = 0, SM_ALPHA = 1, SM_BETA = 2 };
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b, float* __restrict__ x,
+                                                    float* __restrict__ r, float* __restrict__ p,
+                                                    int64_t n, int C, double* __restrict__ partials) {
+  constexpr int R = kBlock / G;
+  const int lane = threadIdx.x % G;
+  const int64_t stride = (int64_t)gridDim.x * R;
+  double dot = 0.0;
+  if (lane < C) {
+    for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
+      const int64_t e = i * C + lane;
+      const float v = b[e];
+      x[e] = 0.f;
+      r[e] = v;
+      p[e] = v;
+      dot += (double)v * (double)v;
+    }
+  }
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = dot;
+  __syncthreads();
+  if ((int)threadIdx.x < C) {
+    double s = 0.0;
+    for (int rr = 0; rr < R; ++rr) s += sh[rr * G + threadIdx.x];
+    partials[(int64_t)blockIdx.x * C + threadIdx.x] = s;
+  }
+}
+
+// Sum the kRedBlocks partials of each column in a fixed order and apply one
+// step of the scalar recurrence.
+__global__ __launch_bounds__(kBlock) void k_cg_scalar(const double* __restrict__ partials, int C,
+                                                      CgState* __restrict__ st, int mode, double tol) {
+  __shared__ double sh[kBlock];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < C; ++c) {
+    double s = 0.0;
+    for (int b = tid; b < kRedBlocks; b += kBlock) s += partials[(int64_t)b * C + c];
+    sh[tid] = s;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (tid < off) sh[tid] += sh[tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double v = sh[0];
+      if (mode == SM_START) {
+        st->rr[c] = v;
+        st->bnorm[c] = sqrt(v);
+        st->active[c] = v > 0.0 ? 1 : 0;
+        st->iters[c] = 0;
+        st->rel[c] = v > 0.0 ? 1.f : 0.f;
+        st->alpha[c] = 0.0;
+        st->beta[c] = 0.0;
+      } else if (mode == SM_ALPHA) {
+        if (st->active[c] && v > 0.0) {
+          st->alpha[c] = st->rr[c] / v;
+        } else {
+          st->alpha[c] = 0.0;
+          st->active[c] = 0;  // converged, or breakdown (p.Ap <= 0)
+        }
+      } else {
+        if (st->active[c]) {
+          st->iters[c] += 1;
+          const double rel = sqrt(v) / st->bnorm[c];
+          st->rel[c] = (float)rel;
+          if (rel <= tol) {
+            st->active[c] = 0;
+            st->beta[c] = 0.0;
+          } else {
+            st->beta[c] = v / st->rr[c];
+            st->rr[c] = v;
+          }
+        } else {
+          st->beta[c] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_cg_update(float* __restrict__ x, float* __restrict__ r,
+                                                      const float* __restrict__ p,
+                                                      const float* __restrict__ q, int64_t n, int C,
+                                                      const CgState* __restrict__ st,
+                                                      double* __restrict__ partials) {
+  constexpr int R = kBlock / G;
+  const int lane = threadIdx.x % G;
+  const int64_t stride = (int64_t)gridDim.x * R;
+  double dot = 0.0;
+  if (lane < C) {
+    const float a = (float)st->alpha[lane];
+    for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
+      const int64_t e = i * C + lane;
+      x[e] = __builtin_fmaf(a, p[e], x[e]);
+      const float rv = __builtin_fmaf(-a, q[e], r[e]);
+      r[e] = rv;
+      dot += (double)rv * (double)rv;
+    }
+  }
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = dot;
+  __syncthreads();
+  if ((int)threadIdx.x < C) {
+    double s = 0.0;
+    for (int rr = 0; rr < R; ++rr) s += sh[rr * G + threadIdx.x];
+    partials[(int64_t)blockIdx.x * C + threadIdx.x] = s;
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_cg_dir(const float* __restrict__ r, float* __restrict__ p,
+                                                   int64_t n, int C, const CgState* __restrict__ st) {
+  constexpr int R = kBlock / G;
+  const int lane = threadIdx.x % G;
+  if (lane >= C || !st->active[lane]) return;
+  const float beta = (float)st->beta[lane];
+  const int64_t stride = (int64_t)gridDim.x * R;
+  for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
+    const int64_t e = i * C + lane;
+    p[e] = __builtin_fmaf(beta, p[e], r[e]);
+  }
+}
+
+template <int G>
+int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, int max_iter,
+         float* x, int32_t* iters, float* rel, hipStream_t s) {
+  sgp_lattice* Lm = const_cast<sgp_lattice*>(L);
+  const int64_t n = L->n, nC = n * C;
+  int rc;
+  if ((rc = dev_reserve(Lm->cgvec, sizeof(float) * 3 * nC))) return rc;
+  const size_t red_bytes = sizeof(double) * kRedBlocks * C + sizeof(CgState) + 256;
+  if ((rc = dev_reserve(Lm->cgred, red_bytes))) return rc;
+  float* r = (float*)Lm->cgvec.ptr;
+  float* p = r + nC;
+  float* q = p + nC;
+  double* partials = (double*)Lm->cgred.ptr;
+  CgState* st = (CgState*)((char*)Lm->cgred.ptr + ((sizeof(double) * kRedBlocks * C + 255) / 256) * 256);
+
+  int32_t* host = nullptr;
+  SGP_HIP(hipHostMalloc((void**)&host, sizeof(int32_t) * 3 * kMaxCgCols, hipHostMallocDefault));
+  struct HostFree {
+    int32_t* p;
+    ~HostFree() { (void)hipHostFree(p); }
+  } host_guard{host};
+
+  const dim3 grid(kRedBlocks), block(kBlock);
+  {
+    ProfScope ps(KK_CG_INIT, s);
+    hipLaunchKernelGGL(k_cg_init<G>, grid, block, 0, s, b, x, r, p, n, C, partials);
+    SGP_LAUNCH_CHECK("k_cg_init");
+  }
+  {
+    ProfScope ps(KK_CG_SCALAR, s);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), block, 0, s, partials, C, st, (int)SM_START, (double)tol);
+    SGP_LAUNCH_CHECK("k_cg_scalar");
+  }
+  // polling interval: each poll drains the queue, so poll less when the
+  // caller asked for a fixed iteration count
+  const int poll = tol > 0.f ? 4 : max_iter;
+  for (int it = 0; it < max_iter; ++it) {
+    if ((rc = mvm_into(L, p, C, q, s, noise, p, partials))) return rc;
+    {
+      ProfScope ps(KK_CG_SCALAR, s);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), block, 0, s, partials, C, st, (int)SM_ALPHA, (double)tol);
+      SGP_LAUNCH_CHECK("k_cg_scalar");
+    }
+    {
+      ProfScope ps(KK_CG_UPDATE, s);
+      hipLaunchKernelGGL(k_cg_update<G>, grid, block, 0, s, x, r, p, q, n, C, st, partials);
+      SGP_LAUNCH_CHECK("k_cg_update");
+    }
+    {
+      ProfScope ps(KK_CG_SCALAR, s);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), block, 0, s, partials, C, st, (int)SM_BETA, (double)tol);
+      SGP_LAUNCH_CHECK("k_cg_scalar");
+    }
+    {
+      ProfScope ps(KK_CG_DIR, s);
+      hipLaunchKernelGGL(k_cg_dir<G>, grid, block, 0, s, r, p, n, C, st);
+      SGP_LAUNCH_CHECK("k_cg_dir");
+    }
+    if ((it + 1) % poll == 0 && it + 1 < max_iter) {
+      SGP_HIP(hipMemcpyAsync(host, st->active, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+      SGP_HIP(hipStreamSynchronize(s));
+      bool any = false;
+      for (int c = 0; c < C; ++c) any |= host[c] != 0;
+      if (!any) break;
+    }
+  }
+  SGP_HIP(hipMemcpyAsync(host, st->iters, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+  SGP_HIP(hipMemcpyAsync(host + kMaxCgCols, st->rel, sizeof(float) * C, hipMemcpyDeviceToHost, s));
+  SGP_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < C; ++c) {
+    if (iters) iters[c] = host[c];
+    if (rel) {
+      float v;
+      memcpy(&v, &host[kMaxCgCols + c], sizeof(float));
+      rel[c] = v;
+    }
+  }
+  return SGP_OK;
+}
+
+}  // namespace
+}  // namespace sgp
+
+using namespace sgp;
+
+extern "C" int cg_solve(const sgp_lattice* L, const float* rhs, int32_t C, float noise, float tol,
+                        int32_t max_iter, float* x, int32_t* iters, float* rel_residual,
+                        void* stream) {
+  if (!L || !rhs || !x) {
+    set_error("cg_solve: NULL argument");
+    return SGP_EINVAL;
+  }
+  if (C < 1 || C > kMaxCgCols) {
+    set_error("cg_solve: need 1 <= C <= %d (got %d)", kMaxCgCols, (int)C);
+    return SGP_EINVAL;
+  }
+  if (!(noise >= 0.f) || !std::isfinite(noise) || !(tol >= 0.f) || !std::isfinite(tol) || max_iter < 1) {
+    set_error("cg_solve: need finite noise >= 0, finite tol >= 0 and max_iter >= 1");
+    return SGP_EINVAL;
+  }
+  const size_t bytes = sizeof(float) * (size_t)L->n * (size_t)C;
+  const char* b0 = (const char*)rhs;
+  const char* x0 = (const char*)x;
+  if (b0 < x0 + bytes && x0 < b0 + bytes) {
+    set_error("cg_solve: x overlaps rhs");
+    return SGP_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  switch (lanes_for(C)) {
+    case 1: return cg_g<1>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
+    case 2: return cg_g<2>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
+    case 4: return cg_g<4>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
+    case 8: return cg_g<8>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
+    case 16: return cg_g<16>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
+    case 32: return cg_g<32>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
+    default: return cg_g<64>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
+  }
+}

@@ -1,0 +1,291 @@
+// Errors, allocation, event profiling, host constants and small API calls.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "sgp_internal.h"
+
+namespace sgp {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  set_error("HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what, file, line);
+  return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
+}
+
+int dev_alloc(DevBuf& b, size_t bytes) {
+  b.ptr = nullptr;
+  b.bytes = 0;
+  if (bytes == 0) return SGP_OK;
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e != hipSuccess) {
+    b.ptr = nullptr;
+    (void)hipGetLastError();
+    set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
+  }
+  b.bytes = bytes;
+  return SGP_OK;
+}
+
+void dev_free(DevBuf& b) {
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+int dev_reserve(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return SGP_OK;
+  if (b.ptr) {
+    // the buffer may still be read by queued work on any stream
+    SGP_HIP(hipDeviceSynchronize());
+    dev_free(b);
+  }
+  return dev_alloc(b, bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Event profiler.
+
+namespace {
+struct ProfRecord {
+  int kind;
+  hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof_pending;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pool;
+int64_t g_prof_launches[KK_NUM] = {};
+double g_prof_ms[KK_NUM] = {};
+const char* const kKindNames[KK_NUM] = {
+    "fill", "simplex_insert", "count_first", "scan", "compact", "resolve", "neighbors",
+    "splat", "blur", "slice", "cg_init", "cg_scalar", "cg_update", "cg_dir"};
+
+// Fold completed records into the totals. Caller holds the mutex.
+int prof_drain() {
+  for (auto& rec : g_prof_pending) {
+    hipError_t e = hipEventSynchronize(rec.stop);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize", __FILE__, __LINE__);
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, rec.start, rec.stop);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime", __FILE__, __LINE__);
+    g_prof_launches[rec.kind] += 1;
+    g_prof_ms[rec.kind] += ms;
+    g_prof_pool.emplace_back(rec.start, rec.stop);
+  }
+  g_prof_pending.clear();
+  return SGP_OK;
+}
+}  // namespace
+
+ProfScope::ProfScope(int kind, hipStream_t s) : stop_(nullptr), stream_(s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!g_prof_pool.empty()) {
+    ev = g_prof_pool.back();
+    g_prof_pool.pop_back();
+  } else {
+    if (hipEventCreate(&ev.first) != hipSuccess) return;
+    if (hipEventCreate(&ev.second) != hipSuccess) {
+      (void)hipEventDestroy(ev.first);
+      return;
+    }
+  }
+  if (hipEventRecord(ev.first, s) != hipSuccess) {
+    g_prof_pool.push_back(ev);
+    return;
+  }
+  g_prof_pending.push_back({kind, ev.first, ev.second});
+  stop_ = ev.second;
+}
+
+ProfScope::~ProfScope() {
+  if (stop_) (void)hipEventRecord(stop_, stream_);
+}
+
+// ---------------------------------------------------------------------------
+// Host constants: stencil spacing (Section 4.1, eq. balance_coverage) and the
+// per-dimension elevation factors (Section 3.2, Splat).
+
+namespace {
+const double kPi = 3.14159265358979323846;
+
+double kernel_at(int kernel, double tau) {
+  tau = std::fabs(tau);
+  if (kernel == SGP_KERNEL_RBF) return std::exp(-0.5 * tau * tau);
+  const double a = std::sqrt(3.0);
+  return (1.0 + a * tau) * std::exp(-a * tau);
+}
+
+// Share of the kernel mass on [-a, a] minus the share of its spectrum on
+// [-b, b]; for the Matern-3/2 kernel both integrals are elementary.
+double coverage_gap_matern32(double a, double b) {
+  const double l3 = std::sqrt(3.0);
+  const double spatial = 1.0 - std::exp(-l3 * a) * (1.0 + l3 * a / 2.0);
+  const double th = std::atan(b / std::sqrt(3.0));
+  const double spectral = (th + 0.5 * std::sin(2.0 * th)) / (kPi / 2.0);
+  return spatial - spectral;
+}
+
+double spacing_for(int kernel, int r) {
+  const int taps = 2 * r + 1;
+  // the Gaussian balance erf(s taps / 2 / sqrt2) = erf(pi / s / sqrt2) has root sqrt(2 pi / taps)
+  if (kernel == SGP_KERNEL_RBF) return std::sqrt(2.0 * kPi / (double)taps);
+  double lo = 1e-3, hi = 1e3;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (coverage_gap_matern32(mid * taps / 2.0, kPi / mid) < 0.0) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+}  // namespace
+
+int make_constants(int d, int r, int kernel, const double* ell, double* spacing, float* stencil,
+                   double* f) {
+  const double s = spacing_for(kernel, r);
+  *spacing = s;
+  for (int t = -r; t <= r; ++t) stencil[t + r] = (float)kernel_at(kernel, t * s);
+  // elevation: column j of the triangular basis has norm sqrt(j(j+1)); one
+  // lattice step (length sqrt(d(d+1))) spans s lengthscales
+  const double alpha = std::sqrt((double)(d * (d + 1))) / s;
+  for (int j = 1; j <= d; ++j) f[j - 1] = alpha / (ell[j - 1] * std::sqrt((double)(j * (j + 1))));
+  return SGP_OK;
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t count, uint32_t value) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = value;
+}
+
+int launch_fill_u32(uint32_t* p, size_t count, uint32_t value, hipStream_t s) {
+  if (count == 0) return SGP_OK;
+  size_t blocks = (count + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  ProfScope ps(KK_FILL, s);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(kBlock), 0, s, p, count, value);
+  SGP_LAUNCH_CHECK("k_fill_u32");
+  return SGP_OK;
+}
+
+}  // namespace sgp
+
+using namespace sgp;
+
+extern "C" {
+
+void sgp_opts_default(sgp_opts* o) {
+  if (!o) return;
+  o->order = 1;
+  o->kernel = SGP_KERNEL_RBF;
+  o->blur = SGP_BLUR_SYMMETRIC;
+  o->outputscale = 1.0f;
+  o->load_factor = 0.5f;
+}
+
+const char* sgp_last_error(void) { return g_err; }
+
+int lattice_info(const sgp_lattice* L, int64_t* n, int32_t* d, int64_t* m, int64_t* device_bytes) {
+  if (!L) {
+    set_error("lattice_info: NULL lattice");
+    return SGP_EINVAL;
+  }
+  if (n) *n = L->n;
+  if (d) *d = L->d;
+  if (m) *m = L->m;
+  if (device_bytes)
+    *device_bytes = (int64_t)(L->idx.bytes + L->w.bytes + L->keys.bytes + L->nbr.bytes +
+                              L->ubuf.bytes + L->cgvec.bytes + L->cgred.bytes);
+  return SGP_OK;
+}
+
+int lattice_export(const sgp_lattice* L, int32_t* keys, int32_t* idx, float* w, int32_t* nbr) {
+  if (!L) {
+    set_error("lattice_export: NULL lattice");
+    return SGP_EINVAL;
+  }
+  SGP_HIP(hipSetDevice(L->device));
+  SGP_HIP(hipDeviceSynchronize());
+  const int D = L->d + 1, T = 2 * L->order;
+  if (keys && L->m) SGP_HIP(hipMemcpy(keys, L->keys.ptr, sizeof(int32_t) * L->m * L->d, hipMemcpyDeviceToHost));
+  if (idx) SGP_HIP(hipMemcpy(idx, L->idx.ptr, sizeof(int32_t) * L->n * D, hipMemcpyDeviceToHost));
+  if (w) SGP_HIP(hipMemcpy(w, L->w.ptr, sizeof(float) * L->n * D, hipMemcpyDeviceToHost));
+  if (nbr && L->m) {
+    // device layout [direction][offset][point] -> [point][direction][offset]
+    std::vector<int32_t> tmp((size_t)D * T * L->m);
+    SGP_HIP(hipMemcpy(tmp.data(), L->nbr.ptr, sizeof(int32_t) * tmp.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < D; ++k)
+      for (int t = 0; t < T; ++t)
+        for (int64_t j = 0; j < L->m; ++j)
+          nbr[((size_t)j * D + k) * T + t] = tmp[((size_t)k * T + t) * L->m + j];
+  }
+  return SGP_OK;
+}
+
+void lattice_free(sgp_lattice* L) {
+  if (!L) return;
+  (void)hipSetDevice(L->device);
+  (void)hipDeviceSynchronize();
+  dev_free(L->idx);
+  dev_free(L->w);
+  dev_free(L->keys);
+  dev_free(L->nbr);
+  dev_free(L->ubuf);
+  dev_free(L->cgvec);
+  dev_free(L->cgred);
+  delete L;
+}
+
+int sgp_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return SGP_OK;
+}
+
+int sgp_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  int rc = prof_drain();
+  for (int k = 0; k < KK_NUM; ++k) {
+    g_prof_launches[k] = 0;
+    g_prof_ms[k] = 0.0;
+  }
+  return rc;
+}
+
+int sgp_profile_kinds(void) { return KK_NUM; }
+
+const char* sgp_profile_name(int kind) {
+  return (kind >= 0 && kind < KK_NUM) ? kKindNames[kind] : "";
+}
+
+int sgp_profile_read(int kind, int64_t* launches, double* total_ms) {
+  if (kind < 0 || kind >= KK_NUM) {
+    set_error("sgp_profile_read: kind %d out of range", kind);
+    return SGP_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  int rc = prof_drain();
+  if (launches) *launches = g_prof_launches[kind];
+  if (total_ms) *total_ms = g_prof_ms[kind];
+  return rc;
+}
+
+}  // extern "C"

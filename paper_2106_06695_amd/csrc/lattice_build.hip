@@ -1,0 +1,626 @@
+// Lattice construction (Section 3.2, Splat and Blur):
+//   k_simplex_insert  elevation, enclosing simplex, barycentric weights, and
+//                     insertion of every simplex vertex into a hash table
+//   k_count_first / k_scan / k_compact
+//                     number the distinct vertices by first occurrence in
+//                     the (point, vertex) order and write their keys
+//   k_resolve         vertex -> lattice index for every (point, vertex),
+//                     with an exact key check that detects hash collisions
+//   k_neighbors       neighbours of every lattice point along the d+1
+//                     lattice directions at offsets -r..r
+//
+// Hash table: open addressing with linear probing over 64-bit key hashes
+// (a slot is claimed by one 64-bit compare-and-swap, so insertion is
+// lock-free and never waits on another lane). Two distinct keys with equal
+// hashes would share a slot; k_resolve compares every vertex key with the
+// stored key of its slot and the host rebuilds with a new seed if any
+// differ, so the final lattice is exact.
+#include <cmath>
+#include <cstring>
+
+#include "sgp_internal.h"
+
+namespace sgp {
+namespace {
+
+enum BuildFlag : uint32_t {
+  BF_NONFINITE = 1u,
+  BF_OVERFLOW = 2u,
+  BF_TABLE_FULL = 4u,
+  BF_COLLISION = 8u
+};
+
+constexpr unsigned long long kEmpty = 0ull;
+constexpr uint32_t kNoFirst = 0xffffffffu;
+constexpr uint32_t kCanonBit = 0x80000000u;  // slot word holds a lattice index
+constexpr double kKeyLimit = 1073741824.0;   // |y_i| bound that keeps keys in int32
+constexpr int kItems = 8;                    // elements per thread in the scan passes
+constexpr int kChunk = kBlock * kItems;
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long h) {
+  h ^= h >> 30;
+  h *= 0xbf58476d1ce4e5b9ull;
+  h ^= h >> 27;
+  h *= 0x94d049bb133111ebull;
+  h ^= h >> 31;
+  return h;
+}
+
+__device__ __forceinline__ unsigned long long hash_step(unsigned long long h, int32_t v) {
+  return mix64(h ^ (unsigned long long)(uint32_t)v) + 0x9e3779b97f4a7c15ull;
+}
+
+__device__ __forceinline__ unsigned long long hash_final(unsigned long long h) {
+  h = mix64(h);
+  return h == kEmpty ? 1ull : h;
+}
+
+struct SimplexArgs {
+  const float* X;
+  int64_t n;
+  int d;
+  double f[kMaxD];
+  float* w;
+  int32_t* pt_r0;
+  uint8_t* pt_rank;
+  int32_t* slot;
+  unsigned long long* tab;
+  uint32_t* tab_first;
+  unsigned long long mask;
+  unsigned long long seed;
+  uint32_t* flags;
+};
+
+// Returns the slot of hash h, claiming an empty one if needed; -1 if full.
+__device__ int64_t table_insert(unsigned long long* tab, unsigned long long mask,
+                                unsigned long long h) {
+  unsigned long long s = h & mask;
+  for (unsigned long long probe = 0; probe <= mask; ++probe) {
+    unsigned long long cur = __hip_atomic_load(&tab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == h) return (int64_t)s;
+    if (cur == kEmpty) {
+      unsigned long long prev = atomicCAS(&tab[s], kEmpty, h);
+      if (prev == kEmpty || prev == h) return (int64_t)s;
+    }
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+// Read-only lookup; -1 if h is not in the table.
+__device__ int64_t table_find(const unsigned long long* tab, unsigned long long mask,
+                              unsigned long long h) {
+  unsigned long long s = h & mask;
+  for (unsigned long long probe = 0; probe <= mask; ++probe) {
+    const unsigned long long cur = tab[s];
+    if (cur == h) return (int64_t)s;
+    if (cur == kEmpty) return -1;
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+// One point per d+1 consecutive lanes: lane j owns coordinate j of the
+// elevated point and, later, vertex j of its simplex. Values other lanes
+// need pass through LDS between barriers. Each floating-point operation
+// rounds once (no contraction), so keys and weights are reproducible.
+__global__ __launch_bounds__(kBlock) void k_simplex_insert(SimplexArgs a) {
+  __shared__ double sh_a[kBlock];    // scaled inputs c_j, then residuals
+  __shared__ double sh_q[kBlock];    // residuals / (d+1) in rank order
+  __shared__ int32_t sh_i[kBlock];   // quotients, then remainder-0 coordinates
+  __shared__ int32_t sh_rk[kBlock];  // ranks after the sum fix
+  __shared__ int32_t sh_bad[kBlock];
+  const int d = a.d, D = d + 1;
+  const int P = kBlock / D;
+  const int tid = threadIdx.x;
+  const int p = tid / D, j = tid - p * D;
+  const int64_t i = (int64_t)blockIdx.x * P + p;
+  const bool live = (p < P) && (i < a.n);
+  const int base = p * D;
+
+  sh_bad[tid] = 0;
+  double cj = 0.0;
+  if (live && j >= 1) cj = (double)a.X[i * d + (j - 1)] * a.f[j - 1];
+  sh_a[tid] = cj;
+  __syncthreads();
+
+  // elevation: y_j = (c_d + c_{d-1} + ... + c_{j+1}) - j c_j, and y_0 = sum of all c
+  double y = 0.0;
+  if (live) {
+    double S = 0.0;
+    for (int l = d; l > j; --l) S = S + sh_a[base + l];
+    y = (j >= 1) ? S - (double)j * cj : S;
+  }
+  uint32_t bad = 0;
+  int32_t q = 0;
+  if (live) {
+    if (isnan(y) || isinf(y)) bad = BF_NONFINITE;
+    else if (!(fabs(y) <= kKeyLimit)) bad = BF_OVERFLOW;
+    else q = (int32_t)rint(y / (double)D);  // nearest multiple of d+1 (ties to even)
+  }
+  sh_i[tid] = q;
+  if (bad) {
+    sh_bad[base] = 1;
+    atomicOr(a.flags, bad);
+  }
+  __syncthreads();
+  const bool ok = live && sh_bad[base] == 0;
+
+  int32_t r0 = q * D;
+  int dsum = 0;
+  if (ok)
+    for (int l = 0; l < D; ++l) dsum += sh_i[base + l];
+  double del = y - (double)r0;
+  sh_a[tid] = del;
+  __syncthreads();
+
+  // rank 0 = largest residual; equal residuals rank the lower index first
+  int rank = 0;
+  if (ok) {
+    for (int l = 0; l < D; ++l) {
+      const double o = sh_a[base + l];
+      rank += (o > del || (o == del && l < j)) ? 1 : 0;
+    }
+    // make the remainder-0 point sum to zero by moving |dsum| coordinates by d+1
+    if (dsum > 0) {
+      if (rank >= D - dsum) { r0 -= D; rank += dsum - D; }
+      else rank += dsum;
+    } else if (dsum < 0) {
+      if (rank < -dsum) { r0 += D; rank += dsum + D; }
+      else rank += dsum;
+    }
+  }
+  rank = min(max(rank, 0), d);
+  del = y - (double)r0;
+  if (ok) sh_q[base + rank] = del / (double)D;
+  sh_i[tid] = r0;
+  sh_rk[tid] = rank;
+  __syncthreads();
+  if (!ok) {
+    if (live) a.slot[i * D + j] = -1;  // rejected point: later passes skip its vertices
+    return;
+  }
+
+  // barycentric weight of vertex k (= this lane): gap between consecutive
+  // sorted residuals; vertex 0 takes the remainder
+  const int k = j;
+  const double b = (k >= 1) ? sh_q[base + d - k] - sh_q[base + d + 1 - k]
+                            : sh_q[base + d] + (1.0 - sh_q[base]);
+  const int64_t e = i * D + k;
+  a.w[e] = (float)b;
+  if (j < d) {
+    a.pt_r0[i * d + j] = r0;
+    a.pt_rank[i * d + j] = (uint8_t)rank;
+  }
+  // vertex k = r0 + canonical vertex s_k permuted by rank (eq. canon_simplex)
+  unsigned long long h = a.seed;
+  for (int l = 0; l < d; ++l) {
+    const int32_t v = sh_i[base + l] + k - (sh_rk[base + l] > d - k ? D : 0);
+    h = hash_step(h, v);
+  }
+  h = hash_final(h);
+  const int64_t s = table_insert(a.tab, a.mask, h);
+  if (s < 0) {
+    atomicOr(a.flags, BF_TABLE_FULL);
+    a.slot[e] = -1;
+    return;
+  }
+  const uint32_t ue = (uint32_t)e;
+  if (__hip_atomic_load(&a.tab_first[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > ue)
+    atomicMin(&a.tab_first[s], ue);
+  a.slot[e] = (int32_t)s;
+}
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
+  __shared__ int sh[kBlock];
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int add = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  const int incl = sh[tid];
+  *total = sh[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__device__ __forceinline__ bool is_first(const int32_t* slot, const uint32_t* tab_first, int64_t e) {
+  const int32_t s = slot[e];
+  return s >= 0 && tab_first[s] == (uint32_t)e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_first(const int32_t* __restrict__ slot,
+                                                        const uint32_t* __restrict__ tab_first,
+                                                        int64_t L, uint32_t* __restrict__ counts) {
+  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
+  int c = 0;
+  for (int u = 0; u < kItems; ++u) {
+    const int64_t e = base + u;
+    if (e < L && is_first(slot, tab_first, e)) ++c;
+  }
+  int total;
+  (void)block_exclusive_scan(c, &total);
+  if (threadIdx.x == 0) counts[blockIdx.x] = (uint32_t)total;
+}
+
+// Exclusive scan of the per-block counts in one block; writes the total m.
+__global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restrict__ counts,
+                                                       uint32_t* __restrict__ offsets, int64_t nb,
+                                                       uint32_t* __restrict__ total) {
+  __shared__ uint32_t sh[kScanThreads];
+  const int tid = threadIdx.x;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kScanThreads) {
+    const uint32_t v = (base + tid < nb) ? counts[base + tid] : 0u;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const uint32_t add = tid >= off ? sh[tid - off] : 0u;
+      __syncthreads();
+      sh[tid] += add;
+      __syncthreads();
+    }
+    if (base + tid < nb) offsets[base + tid] = carry + sh[tid] - v;
+    carry += sh[kScanThreads - 1];
+    __syncthreads();
+  }
+  if (tid == 0) *total = carry;
+}
+
+// Stored coordinate l of vertex k of point i, from its simplex descriptor.
+__device__ __forceinline__ int32_t vertex_coord(const int32_t* pt_r0, const uint8_t* pt_rank,
+                                                int64_t i, int d, int k, int l) {
+  return pt_r0[i * d + l] + k - ((int)pt_rank[i * d + l] > d - k ? d + 1 : 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact(const int32_t* __restrict__ slot,
+                                                    uint32_t* __restrict__ tab_first, int64_t L,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    const int32_t* __restrict__ pt_r0,
+                                                    const uint8_t* __restrict__ pt_rank, int d,
+                                                    int64_t m, int32_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ flags) {
+  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
+  bool flag[kItems];
+  int c = 0;
+  for (int u = 0; u < kItems; ++u) {
+    const int64_t e = base + u;
+    flag[u] = e < L && is_first(slot, tab_first, e);
+    c += flag[u] ? 1 : 0;
+  }
+  int total;
+  uint32_t pos = offsets[blockIdx.x] + (uint32_t)block_exclusive_scan(c, &total);
+  const int D = d + 1;
+  for (int u = 0; u < kItems; ++u) {
+    if (!flag[u]) continue;
+    if ((int64_t)pos >= m) {  // the two counting passes disagree: never expected
+      atomicOr(flags, BF_COLLISION);
+      break;
+    }
+    const int64_t e = base + u;
+    const int64_t i = e / D;
+    const int k = (int)(e - i * D);
+    for (int l = 0; l < d; ++l) keys[(int64_t)pos * d + l] = vertex_coord(pt_r0, pt_rank, i, d, k, l);
+    tab_first[slot[e]] = kCanonBit | pos;
+    ++pos;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_resolve(const int32_t* __restrict__ slot,
+                                                    const uint32_t* __restrict__ tab_first, int64_t L,
+                                                    const int32_t* __restrict__ pt_r0,
+                                                    const uint8_t* __restrict__ pt_rank, int d,
+                                                    const int32_t* __restrict__ keys, int64_t m,
+                                                    int32_t* __restrict__ idx,
+                                                    uint32_t* __restrict__ flags) {
+  const int D = d + 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += stride) {
+    const int32_t s = slot[e];
+    const uint32_t v = s >= 0 ? tab_first[s] : 0u;
+    if (!(v & kCanonBit) || (int64_t)(v & ~kCanonBit) >= m) {
+      idx[e] = 0;
+      atomicOr(flags, BF_COLLISION);
+      continue;
+    }
+    const int32_t j = (int32_t)(v & ~kCanonBit);
+    idx[e] = j;
+    const int64_t i = e / D;
+    const int k = (int)(e - i * D);
+    bool same = true;
+    for (int l = 0; l < d; ++l) same &= keys[(int64_t)j * d + l] == vertex_coord(pt_r0, pt_rank, i, d, k, l);
+    if (!same) atomicOr(flags, BF_COLLISION);
+  }
+}
+
+// Neighbour of lattice point j along direction k at offset t is
+// key + t (1 - (d+1) e_k): +t on every stored coordinate except -t d on
+// coordinate k (for k = d, +t on all of them). Thread g covers (k, j) with
+// j fastest so that the writes to nbr[k][t][j] are contiguous.
+__global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict__ keys, int64_t m,
+                                                      int d, int r,
+                                                      const unsigned long long* __restrict__ tab,
+                                                      const uint32_t* __restrict__ tab_first,
+                                                      unsigned long long mask,
+                                                      unsigned long long seed,
+                                                      int32_t* __restrict__ nbr) {
+  const int D = d + 1, T = 2 * r;
+  const int64_t total = m * D;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+    const int k = (int)(g / m);
+    const int64_t j = g - (int64_t)k * m;
+    const int32_t* kj = keys + j * d;
+    int ti = 0;
+    for (int t = -r; t <= r; ++t) {
+      if (t == 0) continue;
+      unsigned long long h = seed;
+      for (int l = 0; l < d; ++l) h = hash_step(h, kj[l] + (l == k ? -t * d : t));
+      h = hash_final(h);
+      int32_t found = -1;
+      const int64_t s = table_find(tab, mask, h);
+      if (s >= 0) {
+        const uint32_t v = tab_first[s];
+        const int64_t cand = (int64_t)(v & ~kCanonBit);
+        if ((v & kCanonBit) && cand < m) {
+          bool same = true;
+          for (int l = 0; l < d; ++l) same &= keys[cand * d + l] == kj[l] + (l == k ? -t * d : t);
+          if (same) found = (int32_t)cand;
+        }
+      }
+      nbr[((int64_t)k * T + ti) * m + j] = found;
+      ++ti;
+    }
+  }
+}
+
+unsigned grid_for(int64_t work, int64_t per_block, int64_t cap) {
+  int64_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+struct Transient {
+  void* ptr[8] = {};
+  hipStream_t s = nullptr;
+  int alloc(int slot_i, size_t bytes) {
+    hipError_t e = hipMallocAsync(&ptr[slot_i], bytes ? bytes : 16, s);
+    if (e != hipSuccess) {
+      ptr[slot_i] = nullptr;
+      (void)hipGetLastError();
+      set_error("hipMallocAsync of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
+    }
+    return SGP_OK;
+  }
+  ~Transient() {
+    for (void* p : ptr)
+      if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
+int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_factor,
+                  unsigned long long seed, hipStream_t st, uint32_t* host_word, bool* retry) {
+  *retry = false;
+  const int d = L->d, D = d + 1, T = 2 * L->order;
+  const int64_t n = L->n;
+  const int64_t Lel = n * D;
+  int64_t cap = 1024;
+  while ((double)cap * load_factor < (double)Lel) cap <<= 1;
+  if (cap > (int64_t)1 << 31) {
+    set_error("lattice_build: hash table of %lld slots exceeds 2^31; raise load_factor",
+              (long long)cap);
+    return SGP_EINVAL;
+  }
+  const int64_t nb = (Lel + kChunk - 1) / kChunk;
+
+  Transient tr;
+  tr.s = st;
+  int rc;
+  enum { T_R0, T_RANK, T_SLOT, T_TAB, T_FIRST, T_COUNTS, T_OFFS, T_WORDS };
+  if ((rc = tr.alloc(T_R0, sizeof(int32_t) * n * d))) return rc;
+  if ((rc = tr.alloc(T_RANK, sizeof(uint8_t) * n * d))) return rc;
+  if ((rc = tr.alloc(T_SLOT, sizeof(int32_t) * Lel))) return rc;
+  if ((rc = tr.alloc(T_TAB, sizeof(unsigned long long) * cap))) return rc;
+  if ((rc = tr.alloc(T_FIRST, sizeof(uint32_t) * cap))) return rc;
+  if ((rc = tr.alloc(T_COUNTS, sizeof(uint32_t) * nb))) return rc;
+  if ((rc = tr.alloc(T_OFFS, sizeof(uint32_t) * nb))) return rc;
+  if ((rc = tr.alloc(T_WORDS, sizeof(uint32_t) * 4))) return rc;
+  int32_t* pt_r0 = (int32_t*)tr.ptr[T_R0];
+  uint8_t* pt_rank = (uint8_t*)tr.ptr[T_RANK];
+  int32_t* slot = (int32_t*)tr.ptr[T_SLOT];
+  unsigned long long* tab = (unsigned long long*)tr.ptr[T_TAB];
+  uint32_t* tab_first = (uint32_t*)tr.ptr[T_FIRST];
+  uint32_t* counts = (uint32_t*)tr.ptr[T_COUNTS];
+  uint32_t* offs = (uint32_t*)tr.ptr[T_OFFS];
+  uint32_t* words = (uint32_t*)tr.ptr[T_WORDS];  // [0] flags, [1] m
+
+  if ((rc = launch_fill_u32((uint32_t*)tab, (size_t)cap * 2, 0u, st))) return rc;
+  if ((rc = launch_fill_u32(tab_first, (size_t)cap, kNoFirst, st))) return rc;
+  if ((rc = launch_fill_u32(words, 4, 0u, st))) return rc;
+
+  SimplexArgs a;
+  a.X = X;
+  a.n = n;
+  a.d = d;
+  for (int j = 0; j < kMaxD; ++j) a.f[j] = j < d ? f[j] : 0.0;
+  a.w = (float*)L->w.ptr;
+  a.pt_r0 = pt_r0;
+  a.pt_rank = pt_rank;
+  a.slot = slot;
+  a.tab = tab;
+  a.tab_first = tab_first;
+  a.mask = (unsigned long long)(cap - 1);
+  a.seed = seed;
+  a.flags = words;
+  const int P = kBlock / D;
+  {
+    ProfScope ps(KK_SIMPLEX, st);
+    hipLaunchKernelGGL(k_simplex_insert, dim3(grid_for(n, P, INT32_MAX)), dim3(kBlock), 0, st, a);
+    SGP_LAUNCH_CHECK("k_simplex_insert");
+  }
+  {
+    ProfScope ps(KK_COUNT, st);
+    hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel,
+                       counts);
+    SGP_LAUNCH_CHECK("k_count_first");
+  }
+  {
+    ProfScope ps(KK_SCAN, st);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, counts, offs, nb, words + 1);
+    SGP_LAUNCH_CHECK("k_scan");
+  }
+  SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, st));
+  SGP_HIP(hipStreamSynchronize(st));
+  const uint32_t flags = host_word[0];
+  const int64_t m = host_word[1];
+  if (flags & BF_NONFINITE) {
+    set_error("lattice_build: X contains NaN or Inf");
+    return SGP_EINVAL;
+  }
+  if (flags & BF_OVERFLOW) {
+    set_error("lattice_build: |x|/lengthscale too large, a lattice coordinate leaves int32");
+    return SGP_EOVERFLOW;
+  }
+  if (flags & BF_TABLE_FULL) {
+    set_error("lattice_build: hash table full");
+    return SGP_EHASH;
+  }
+  if (m < 1 || m > Lel) {
+    set_error("lattice_build: inconsistent lattice size %lld", (long long)m);
+    return SGP_EHASH;
+  }
+  L->m = m;
+  dev_free(L->keys);
+  dev_free(L->nbr);
+  if ((rc = dev_alloc(L->keys, sizeof(int32_t) * m * d))) return rc;
+  if ((rc = dev_alloc(L->nbr, sizeof(int32_t) * m * D * T))) return rc;
+  {
+    ProfScope ps(KK_COMPACT, st);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel, offs,
+                       pt_r0, pt_rank, d, m, (int32_t*)L->keys.ptr, words);
+    SGP_LAUNCH_CHECK("k_compact");
+  }
+  {
+    ProfScope ps(KK_RESOLVE, st);
+    hipLaunchKernelGGL(k_resolve, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, slot,
+                       tab_first, Lel, pt_r0, pt_rank, d, (const int32_t*)L->keys.ptr, m,
+                       (int32_t*)L->idx.ptr, words);
+    SGP_LAUNCH_CHECK("k_resolve");
+  }
+  {
+    ProfScope ps(KK_NEIGHBORS, st);
+    hipLaunchKernelGGL(k_neighbors, dim3(grid_for(m * D, kBlock, 16384)), dim3(kBlock), 0, st,
+                       (const int32_t*)L->keys.ptr, m, d, L->order, tab, tab_first,
+                       (unsigned long long)(cap - 1), seed, (int32_t*)L->nbr.ptr);
+    SGP_LAUNCH_CHECK("k_neighbors");
+  }
+  SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  SGP_HIP(hipStreamSynchronize(st));
+  if (host_word[0] & BF_COLLISION) *retry = true;
+  return SGP_OK;
+}
+
+}  // namespace
+}  // namespace sgp
+
+using namespace sgp;
+
+extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double* lengthscales,
+                             const sgp_opts* opts, void* stream, sgp_lattice** out) {
+  if (!out) {
+    set_error("lattice_build: out is NULL");
+    return SGP_EINVAL;
+  }
+  *out = nullptr;
+  sgp_opts o;
+  sgp_opts_default(&o);
+  if (opts) o = *opts;
+  if (!X || !lengthscales) {
+    set_error("lattice_build: X and lengthscales must be non-NULL");
+    return SGP_EINVAL;
+  }
+  if (n < 1 || d < 1 || d > kMaxD) {
+    set_error("lattice_build: need n >= 1 and 1 <= d <= %d (got n=%lld, d=%d)", kMaxD,
+              (long long)n, (int)d);
+    return SGP_EINVAL;
+  }
+  if (n > ((int64_t)1 << 30) / (d + 1)) {
+    set_error("lattice_build: n*(d+1) must not exceed 2^30");
+    return SGP_EINVAL;
+  }
+  for (int j = 0; j < d; ++j) {
+    if (!(lengthscales[j] > 0.0) || !std::isfinite(lengthscales[j])) {
+      set_error("lattice_build: lengthscale %d is not finite and positive", j);
+      return SGP_EINVAL;
+    }
+  }
+  if (o.order < 1 || o.order > kMaxOrder) {
+    set_error("lattice_build: order must be in 1..%d", kMaxOrder);
+    return SGP_EINVAL;
+  }
+  if (o.kernel != SGP_KERNEL_RBF && o.kernel != SGP_KERNEL_MATERN32) {
+    set_error("lattice_build: unknown kernel %d", o.kernel);
+    return SGP_EINVAL;
+  }
+  if (o.blur != SGP_BLUR_SYMMETRIC && o.blur != SGP_BLUR_FORWARD && o.blur != SGP_BLUR_REVERSE) {
+    set_error("lattice_build: unknown blur order %d", o.blur);
+    return SGP_EINVAL;
+  }
+  if (!std::isfinite(o.outputscale)) {
+    set_error("lattice_build: outputscale must be finite");
+    return SGP_EINVAL;
+  }
+  if (!(o.load_factor > 0.0f && o.load_factor <= 0.9f)) {
+    set_error("lattice_build: load_factor must be in (0, 0.9]");
+    return SGP_EINVAL;
+  }
+
+  hipStream_t st = (hipStream_t)stream;
+  sgp_lattice* L = new sgp_lattice();
+  L->n = n;
+  L->d = d;
+  L->order = o.order;
+  L->kernel = o.kernel;
+  L->blur = o.blur;
+  L->outputscale = o.outputscale;
+  double f[kMaxD];
+  make_constants(d, o.order, o.kernel, lengthscales, &L->spacing, L->stencil, f);
+
+  int rc = SGP_OK;
+  uint32_t* host_word = nullptr;
+  {
+    hipError_t e = hipGetDevice(&L->device);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&host_word, 16, hipHostMallocDefault);
+    if (e != hipSuccess) rc = hip_fail(e, "lattice_build setup", __FILE__, __LINE__);
+  }
+  const int D = d + 1;
+  if (rc == SGP_OK) rc = dev_alloc(L->idx, sizeof(int32_t) * n * D);
+  if (rc == SGP_OK) rc = dev_alloc(L->w, sizeof(float) * n * D);
+  bool retry = true;
+  for (int attempt = 0; rc == SGP_OK && retry && attempt < 4; ++attempt) {
+    const unsigned long long seed = 0x5157a11ce5eedull + 0x9e3779b97f4a7c15ull * (unsigned long long)attempt;
+    rc = build_attempt(L, X, f, (double)o.load_factor, seed, st, host_word, &retry);
+  }
+  if (rc == SGP_OK && retry) {
+    set_error("lattice_build: hash verification failed after 4 seeds");
+    rc = SGP_EHASH;
+  }
+  if (rc == SGP_OK) {
+    hipError_t e = hipStreamSynchronize(st);  // transient buffers are released on the stream
+    if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
+  }
+  if (host_word) (void)hipHostFree(host_word);
+  if (rc != SGP_OK) {
+    lattice_free(L);
+    return rc;
+  }
+  *out = L;
+  return SGP_OK;
+}
