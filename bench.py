@@ -29,24 +29,28 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, cg: bool) -> float:
-    """Algorithmic HBM bytes of ONE launch of a kernel kind (fp32 values,
-    int32 indices; every array touched once per launch)."""
+    """Algorithmic HBM bytes of ONE launch of a kernel kind: int32 indices,
+    fp32 weights, every array touched once per launch. Inside CG (cg=True)
+    the values and lattice accumulators are fp64, in lattice_mvm fp32."""
     D, T = d + 1, 2 * r
     chains = 2 if sym else 1
-    if kind == "splat":   # idx + w, V in, U out
-        return n * D * 8 + n * C * 4 + m * C * 4
-    if kind == "slice":   # idx + w, U (both chains) in, out (+ p in CG)
-        return n * D * 8 + chains * m * C * 4 + n * C * 4 + (n * C * 4 if cg else 0)
-    if kind == "blur":    # per chain: U in, U out, neighbour lists
-        return chains * (2 * m * C * 4 + T * m * 4)
-    if kind == "cg_update":  # x, p, q, r in; x, r out
-        return 6 * n * C * 4
-    if kind == "cg_dir":     # r, p in; p out
-        return 3 * n * C * 4
-    if kind == "cg_init":    # b in; x, r, p out
-        return 4 * n * C * 4
+    vb = ub = 8 if cg else 4
+    if kind == "splat":      # idx + w, V in, U out
+        return n * D * 8 + n * C * vb + m * C * ub
+    if kind == "slice":      # idx + w, U (both chains) in, out (+ p in CG)
+        return n * D * 8 + chains * m * C * ub + n * C * vb + (n * C * vb if cg else 0)
+    if kind == "blur":       # per chain: U in, U out, neighbour lists
+        return chains * (2 * m * C * ub + T * m * 4)
+    if kind == "cg_update":  # x, p, q, r in; x, r out (fp64)
+        return 6 * n * C * 8
+    if kind == "cg_dir":     # r, p in; p out (fp64)
+        return 3 * n * C * 8
+    if kind == "cg_init":    # b in (fp32); x, r, p out (fp64)
+        return n * C * 4 + 3 * n * C * 8
+    if kind == "cg_out":     # x in (fp64), x out (fp32)
+        return n * C * 12
     if kind == "fill":
-        return m * C * 4
+        return m * C * ub
     return 0.0
 
 
@@ -155,7 +159,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64 CG vectors and lattice accumulation, f32 weights",
         "data": "synthetic",
         "config": {"workload": "ws3: n=2,000,000 d=11 X from a 50-component Gaussian mixture "
                                "(standardised), lengthscales logU[0.5,2], C=16 (1 target + 15 "

@@ -6,7 +6,12 @@
 // second one-block kernel decides convergence and beta. The host only polls
 // the per-column "active" flags every few iterations.
 //
-// Partial sums are reduced in a fixed order in fp64, so a run is
+// Precision: the solver's vectors (x, r, p, q), the lattice values inside
+// its MVMs and all reductions are fp64; only the barycentric weights stay
+// fp32. In fp32 the recursive residual drifts from the true one by about
+// eps * cond(A), which at the conditioning of typical GP systems
+// (cond ~ 1e3..1e4) is already above a 1e-4 tolerance. The caller's rhs and
+// x are fp32. Partial sums are reduced in a fixed order, so a run is
 // reproducible given the MVM's own rounding.
 #include <cmath>
 #include <cstring>
@@ -29,8 +34,8 @@ struct CgState {
 enum ScalarMode { SM_START = 0, SM_ALPHA = 1, SM_BETA = 2 };
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b, float* __restrict__ x,
-                                                    float* __restrict__ r, float* __restrict__ p,
+__global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b, double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ p,
                                                     int64_t n, int C, double* __restrict__ partials) {
   constexpr int R = kBlock / G;
   const int lane = threadIdx.x % G;
@@ -39,11 +44,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
   if (lane < C) {
     for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
       const int64_t e = i * C + lane;
-      const float v = b[e];
-      x[e] = 0.f;
+      const double v = (double)b[e];
+      x[e] = 0.0;
       r[e] = v;
       p[e] = v;
-      dot += (double)v * (double)v;
+      dot += v * v;
     }
   }
   __shared__ double sh[kBlock];
@@ -110,9 +115,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_scalar(const double* __restrict__
 }
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_cg_update(float* __restrict__ x, float* __restrict__ r,
-                                                      const float* __restrict__ p,
-                                                      const float* __restrict__ q, int64_t n, int C,
+__global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q, int64_t n, int C,
                                                       const CgState* __restrict__ st,
                                                       double* __restrict__ partials) {
   constexpr int R = kBlock / G;
@@ -120,13 +125,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(float* __restrict__ x, flo
   const int64_t stride = (int64_t)gridDim.x * R;
   double dot = 0.0;
   if (lane < C) {
-    const float a = (float)st->alpha[lane];
+    const double a = st->alpha[lane];
     for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
       const int64_t e = i * C + lane;
-      x[e] = __builtin_fmaf(a, p[e], x[e]);
-      const float rv = __builtin_fmaf(-a, q[e], r[e]);
+      x[e] = __builtin_fma(a, p[e], x[e]);
+      const double rv = __builtin_fma(-a, q[e], r[e]);
       r[e] = rv;
-      dot += (double)rv * (double)rv;
+      dot += rv * rv;
     }
   }
   __shared__ double sh[kBlock];
@@ -140,17 +145,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(float* __restrict__ x, flo
 }
 
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_cg_dir(const float* __restrict__ r, float* __restrict__ p,
+__global__ __launch_bounds__(kBlock) void k_cg_dir(const double* __restrict__ r, double* __restrict__ p,
                                                    int64_t n, int C, const CgState* __restrict__ st) {
   constexpr int R = kBlock / G;
   const int lane = threadIdx.x % G;
   if (lane >= C || !st->active[lane]) return;
-  const float beta = (float)st->beta[lane];
+  const double beta = st->beta[lane];
   const int64_t stride = (int64_t)gridDim.x * R;
   for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
     const int64_t e = i * C + lane;
-    p[e] = __builtin_fmaf(beta, p[e], r[e]);
+    p[e] = __builtin_fma(beta, p[e], r[e]);
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_out(const double* __restrict__ x64, float* __restrict__ x,
+                                                   int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride)
+    x[e] = (float)x64[e];
 }
 
 template <int G>
@@ -159,12 +171,13 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   sgp_lattice* Lm = const_cast<sgp_lattice*>(L);
   const int64_t n = L->n, nC = n * C;
   int rc;
-  if ((rc = dev_reserve(Lm->cgvec, sizeof(float) * 3 * nC))) return rc;
+  if ((rc = dev_reserve(Lm->cgvec, sizeof(double) * 4 * nC))) return rc;
   const size_t red_bytes = sizeof(double) * kRedBlocks * C + sizeof(CgState) + 256;
   if ((rc = dev_reserve(Lm->cgred, red_bytes))) return rc;
-  float* r = (float*)Lm->cgvec.ptr;
-  float* p = r + nC;
-  float* q = p + nC;
+  double* x64 = (double*)Lm->cgvec.ptr;
+  double* r = x64 + nC;
+  double* p = r + nC;
+  double* q = p + nC;
   double* partials = (double*)Lm->cgred.ptr;
   CgState* st = (CgState*)((char*)Lm->cgred.ptr + ((sizeof(double) * kRedBlocks * C + 255) / 256) * 256);
 
@@ -178,7 +191,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   const dim3 grid(kRedBlocks), block(kBlock);
   {
     ProfScope ps(KK_CG_INIT, s);
-    hipLaunchKernelGGL(k_cg_init<G>, grid, block, 0, s, b, x, r, p, n, C, partials);
+    hipLaunchKernelGGL(k_cg_init<G>, grid, block, 0, s, b, x64, r, p, n, C, partials);
     SGP_LAUNCH_CHECK("k_cg_init");
   }
   {
@@ -190,7 +203,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   // caller asked for a fixed iteration count
   const int poll = tol > 0.f ? 4 : max_iter;
   for (int it = 0; it < max_iter; ++it) {
-    if ((rc = mvm_into(L, p, C, q, s, noise, p, partials))) return rc;
+    if ((rc = mvm_cg(L, p, C, q, s, (double)noise, partials))) return rc;
     {
       ProfScope ps(KK_CG_SCALAR, s);
       hipLaunchKernelGGL(k_cg_scalar, dim3(1), block, 0, s, partials, C, st, (int)SM_ALPHA, (double)tol);
@@ -198,7 +211,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     }
     {
       ProfScope ps(KK_CG_UPDATE, s);
-      hipLaunchKernelGGL(k_cg_update<G>, grid, block, 0, s, x, r, p, q, n, C, st, partials);
+      hipLaunchKernelGGL(k_cg_update<G>, grid, block, 0, s, x64, r, p, q, n, C, st, partials);
       SGP_LAUNCH_CHECK("k_cg_update");
     }
     {
@@ -218,6 +231,11 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
       for (int c = 0; c < C; ++c) any |= host[c] != 0;
       if (!any) break;
     }
+  }
+  {
+    ProfScope ps(KK_CG_OUT, s);
+    hipLaunchKernelGGL(k_cg_out, dim3(kRedBlocks), block, 0, s, x64, x, nC);
+    SGP_LAUNCH_CHECK("k_cg_out");
   }
   SGP_HIP(hipMemcpyAsync(host, st->iters, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
   SGP_HIP(hipMemcpyAsync(host + kMaxCgCols, st->rel, sizeof(float) * C, hipMemcpyDeviceToHost, s));

@@ -73,7 +73,7 @@ int64_t g_prof_launches[KK_NUM] = {};
 double g_prof_ms[KK_NUM] = {};
 const char* const kKindNames[KK_NUM] = {
     "fill", "simplex_insert", "count_first", "scan", "compact", "resolve", "neighbors",
-    "splat", "blur", "slice", "cg_init", "cg_scalar", "cg_update", "cg_dir"};
+    "splat", "blur", "slice", "cg_init", "cg_scalar", "cg_update", "cg_dir", "cg_out"};
 
 // Fold completed records into the totals. Caller holds the mutex.
 int prof_drain() {
@@ -156,11 +156,11 @@ double spacing_for(int kernel, int r) {
 }
 }  // namespace
 
-int make_constants(int d, int r, int kernel, const double* ell, double* spacing, float* stencil,
+int make_constants(int d, int r, int kernel, const double* ell, double* spacing, double* stencil,
                    double* f) {
   const double s = spacing_for(kernel, r);
   *spacing = s;
-  for (int t = -r; t <= r; ++t) stencil[t + r] = (float)kernel_at(kernel, t * s);
+  for (int t = -r; t <= r; ++t) stencil[t + r] = kernel_at(kernel, t * s);
   // elevation: column j of the triangular basis has norm sqrt(j(j+1)); one
   // lattice step (length sqrt(d(d+1))) spans s lengthscales
   const double alpha = std::sqrt((double)(d * (d + 1))) / s;

@@ -591,7 +591,7 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
   L->blur = o.blur;
   L->outputscale = o.outputscale;
   double f[kMaxD];
-  make_constants(d, o.order, o.kernel, lengthscales, &L->spacing, L->stencil, f);
+  make_constants(d, o.order, o.kernel, lengthscales, &L->spacing, L->stencil64, f);
 
   int rc = SGP_OK;
   uint32_t* host_word = nullptr;

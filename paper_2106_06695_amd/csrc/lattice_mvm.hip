@@ -17,11 +17,11 @@
 namespace sgp {
 namespace {
 
-template <int G>
+template <typename TV, typename TU, int G>
 __global__ __launch_bounds__(kBlock) void k_splat(const int32_t* __restrict__ idx,
                                                   const float* __restrict__ w,
-                                                  const float* __restrict__ V,
-                                                  float* __restrict__ U, int64_t n, int D, int C) {
+                                                  const TV* __restrict__ V,
+                                                  TU* __restrict__ U, int64_t n, int D, int C) {
   constexpr int R = kBlock / G;
   const int lane = threadIdx.x % G;
   const int64_t stride = (int64_t)gridDim.x * R;
@@ -29,25 +29,29 @@ __global__ __launch_bounds__(kBlock) void k_splat(const int32_t* __restrict__ id
     const int32_t* ii = idx + i * D;
     const float* wi = w + i * D;
     for (int c = lane; c < C; c += G) {
-      const float v = V[i * C + c];
-      for (int k = 0; k < D; ++k) unsafeAtomicAdd(&U[(int64_t)ii[k] * C + c], wi[k] * v);
+      const TU v = (TU)V[i * C + c];
+      for (int k = 0; k < D; ++k) unsafeAtomicAdd(&U[(int64_t)ii[k] * C + c], (TU)wi[k] * v);
     }
   }
 }
 
+template <typename TU>
 struct BlurArgs {
-  const float* in[2];
-  float* out[2];
+  const TU* in[2];
+  TU* out[2];
   const int32_t* nbr[2];  // neighbour table of this step's direction, per chain
   int64_t m;
   int C;
   int r;
   int chains;
-  float st[2 * kMaxOrder + 1];
+  TU st[2 * kMaxOrder + 1];
 };
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_blur(BlurArgs a) {
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename TU, int G>
+__global__ __launch_bounds__(kBlock) void k_blur(BlurArgs<TU> a) {
   constexpr int R = kBlock / G;
   const int lane = threadIdx.x % G;
   const int64_t rows = a.m * a.chains;
@@ -56,35 +60,35 @@ __global__ __launch_bounds__(kBlock) void k_blur(BlurArgs a) {
   for (int64_t q = (int64_t)blockIdx.x * R + threadIdx.x / G; q < rows; q += stride) {
     const int ch = q >= a.m ? 1 : 0;
     const int64_t j = q - (ch ? a.m : 0);
-    const float* in = a.in[ch];
+    const TU* in = a.in[ch];
     const int32_t* nb = a.nbr[ch] + j;
     for (int c = lane; c < C; c += G) {
-      float acc = 0.f;
+      TU acc = 0;
       int ti = 0;
       for (int t = -r; t <= r; ++t) {
-        float u;
+        TU u;
         if (t == 0) {
           u = in[j * C + c];
         } else {
           const int32_t x = nb[(int64_t)ti * a.m];
-          u = x >= 0 ? in[(int64_t)x * C + c] : 0.f;
+          u = x >= 0 ? in[(int64_t)x * C + c] : (TU)0;
           ++ti;
         }
-        acc = __builtin_fmaf(a.st[t + r], u, acc);
+        acc = fma_t(a.st[t + r], u, acc);
       }
       a.out[ch][j * C + c] = acc;
     }
   }
 }
 
-template <int G, bool SYM, bool CG>
+template <typename TV, typename TU, int G, bool SYM, bool CG>
 __global__ __launch_bounds__(kBlock) void k_slice(const int32_t* __restrict__ idx,
                                                   const float* __restrict__ w,
-                                                  const float* __restrict__ UF,
-                                                  const float* __restrict__ UR,
-                                                  float* __restrict__ out, int64_t n, int D, int C,
-                                                  float scale, float noise,
-                                                  const float* __restrict__ p,
+                                                  const TU* __restrict__ UF,
+                                                  const TU* __restrict__ UR,
+                                                  TV* __restrict__ out, int64_t n, int D, int C,
+                                                  TU scale, TV noise,
+                                                  const TV* __restrict__ p,
                                                   double* __restrict__ partials) {
   constexpr int R = kBlock / G;
   const int lane = threadIdx.x % G;
@@ -94,17 +98,17 @@ __global__ __launch_bounds__(kBlock) void k_slice(const int32_t* __restrict__ id
     const int32_t* ii = idx + i * D;
     const float* wi = w + i * D;
     for (int c = lane; c < C; c += G) {
-      float acc = 0.f;
+      TU acc = 0;
       for (int k = 0; k < D; ++k) {
         const int64_t row = (int64_t)ii[k] * C + c;
-        float u = UF[row];
+        TU u = UF[row];
         if (SYM) u += UR[row];
-        acc = __builtin_fmaf(wi[k], u, acc);
+        acc = fma_t((TU)wi[k], u, acc);
       }
-      float o = scale * acc;
+      TV o = (TV)(scale * acc);
       if (CG) {
-        const float pv = p[i * C + c];
-        o = __builtin_fmaf(noise, pv, o);
+        const TV pv = p[i * C + c];
+        o = fma_t(noise, pv, o);
         dot += (double)pv * (double)o;
       }
       out[i * C + c] = o;
@@ -130,98 +134,108 @@ unsigned grid_rows(int64_t rows, int G, int64_t cap) {
   return (unsigned)b;
 }
 
-template <int G>
-int launch_splat(const sgp_lattice* L, const float* V, int C, float* U, hipStream_t s) {
+template <typename TV, typename TU, int G>
+int launch_splat(const sgp_lattice* L, const TV* V, int C, TU* U, hipStream_t s) {
   ProfScope ps(KK_SPLAT, s);
-  hipLaunchKernelGGL(k_splat<G>, dim3(grid_rows(L->n, G, 32768)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((k_splat<TV, TU, G>), dim3(grid_rows(L->n, G, 32768)), dim3(kBlock), 0, s,
                      (const int32_t*)L->idx.ptr, (const float*)L->w.ptr, V, U, L->n, L->d + 1, C);
   SGP_LAUNCH_CHECK("k_splat");
   return SGP_OK;
 }
 
-template <int G>
-int launch_blur(const BlurArgs& a, hipStream_t s) {
+template <typename TU, int G>
+int launch_blur(const BlurArgs<TU>& a, hipStream_t s) {
   ProfScope ps(KK_BLUR, s);
-  hipLaunchKernelGGL(k_blur<G>, dim3(grid_rows(a.m * a.chains, G, 32768)), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((k_blur<TU, G>), dim3(grid_rows(a.m * a.chains, G, 32768)), dim3(kBlock), 0, s, a);
   SGP_LAUNCH_CHECK("k_blur");
   return SGP_OK;
 }
 
-template <int G, bool SYM, bool CG>
-int launch_slice(const sgp_lattice* L, const float* UF, const float* UR, float* out, int C,
-                 float scale, float noise, const float* p, double* partials, hipStream_t s) {
+template <typename TV, typename TU, int G, bool SYM, bool CG>
+int launch_slice(const sgp_lattice* L, const TU* UF, const TU* UR, TV* out, int C, TU scale,
+                 TV noise, const TV* p, double* partials, hipStream_t s) {
   ProfScope ps(KK_SLICE, s);
   const unsigned grid = CG ? (unsigned)kRedBlocks : grid_rows(L->n, G, 32768);
-  hipLaunchKernelGGL((k_slice<G, SYM, CG>), dim3(grid), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((k_slice<TV, TU, G, SYM, CG>), dim3(grid), dim3(kBlock), 0, s,
                      (const int32_t*)L->idx.ptr, (const float*)L->w.ptr, UF, UR, out, L->n,
                      L->d + 1, C, scale, noise, p, partials);
   SGP_LAUNCH_CHECK("k_slice");
   return SGP_OK;
 }
 
-template <int G>
-int mvm_g(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s, float noise,
-          const float* p, double* partials) {
+template <typename TV, typename TU, int G>
+int mvm_g(const sgp_lattice* L, const TV* V, int C, TV* out, hipStream_t s, TV noise, const TV* p,
+          double* partials) {
   const int d = L->d, T = 2 * L->order;
   const int64_t m = L->m, mC = m * C;
-  float* U0 = (float*)L->ubuf.ptr;
-  float* B1 = U0 + mC;
-  float* B2 = B1 + mC;
-  float* B3 = B2 + mC;
+  TU* U0 = (TU*)L->ubuf.ptr;
+  TU* B1 = U0 + mC;
+  TU* B2 = B1 + mC;
+  TU* B3 = B2 + mC;
   int rc;
-  if ((rc = launch_fill_u32((uint32_t*)U0, (size_t)mC, 0u, s))) return rc;
-  if ((rc = launch_splat<G>(L, V, C, U0, s))) return rc;
+  if ((rc = launch_fill_u32((uint32_t*)U0, (size_t)mC * sizeof(TU) / 4, 0u, s))) return rc;
+  if ((rc = launch_splat<TV, TU, G>(L, V, C, U0, s))) return rc;
 
   const bool sym = L->blur == SGP_BLUR_SYMMETRIC;
-  BlurArgs a;
+  BlurArgs<TU> a;
   a.m = m;
   a.C = C;
   a.r = L->order;
   a.chains = sym ? 2 : 1;
-  for (int t = 0; t < 2 * L->order + 1; ++t) a.st[t] = L->stencil[t];
+  for (int t = 0; t < 2 * L->order + 1; ++t) a.st[t] = (TU)L->stencil64[t];
   const int32_t* nbr = (const int32_t*)L->nbr.ptr;
-  const float* cur[2] = {U0, U0};
+  const TU* cur[2] = {U0, U0};
   for (int step = 0; step <= d; ++step) {
     // chain 0: forward (or the single requested order); chain 1: reverse
     const int k0 = (L->blur == SGP_BLUR_REVERSE) ? d - step : step;
     const int k1 = d - step;
-    float* dst0 = (step % 2 == 0) ? B1 : B2;
-    float* dst1 = (step % 2 == 0) ? B3 : U0;
+    TU* dst0 = (step % 2 == 0) ? B1 : B2;
+    TU* dst1 = (step % 2 == 0) ? B3 : U0;
     a.in[0] = cur[0];
     a.out[0] = dst0;
     a.nbr[0] = nbr + (int64_t)k0 * T * m;
     a.in[1] = cur[1];
     a.out[1] = dst1;
     a.nbr[1] = nbr + (int64_t)k1 * T * m;
-    if ((rc = launch_blur<G>(a, s))) return rc;
+    if ((rc = launch_blur<TU, G>(a, s))) return rc;
     cur[0] = dst0;
     cur[1] = dst1;
   }
   const bool cg = partials != nullptr;
-  const float scale = sym ? 0.5f * L->outputscale : L->outputscale;
+  const TU scale = sym ? (TU)(0.5 * (double)L->outputscale) : (TU)L->outputscale;
   if (sym) {
-    return cg ? launch_slice<G, true, true>(L, cur[0], cur[1], out, C, scale, noise, p, partials, s)
-              : launch_slice<G, true, false>(L, cur[0], cur[1], out, C, scale, 0.f, nullptr, nullptr, s);
+    return cg ? launch_slice<TV, TU, G, true, true>(L, cur[0], cur[1], out, C, scale, noise, p, partials, s)
+              : launch_slice<TV, TU, G, true, false>(L, cur[0], cur[1], out, C, scale, (TV)0, nullptr, nullptr, s);
   }
-  return cg ? launch_slice<G, false, true>(L, cur[0], nullptr, out, C, scale, noise, p, partials, s)
-            : launch_slice<G, false, false>(L, cur[0], nullptr, out, C, scale, 0.f, nullptr, nullptr, s);
+  return cg ? launch_slice<TV, TU, G, false, true>(L, cur[0], nullptr, out, C, scale, noise, p, partials, s)
+            : launch_slice<TV, TU, G, false, false>(L, cur[0], nullptr, out, C, scale, (TV)0, nullptr, nullptr, s);
+}
+
+template <typename TV, typename TU>
+int mvm_dispatch(const sgp_lattice* L, const TV* V, int C, TV* out, hipStream_t s, TV noise,
+                 const TV* p, double* partials) {
+  int rc = dev_reserve(const_cast<sgp_lattice*>(L)->ubuf, sizeof(TU) * 4 * L->m * C);
+  if (rc) return rc;
+  switch (lanes_for(C)) {
+    case 1: return mvm_g<TV, TU, 1>(L, V, C, out, s, noise, p, partials);
+    case 2: return mvm_g<TV, TU, 2>(L, V, C, out, s, noise, p, partials);
+    case 4: return mvm_g<TV, TU, 4>(L, V, C, out, s, noise, p, partials);
+    case 8: return mvm_g<TV, TU, 8>(L, V, C, out, s, noise, p, partials);
+    case 16: return mvm_g<TV, TU, 16>(L, V, C, out, s, noise, p, partials);
+    case 32: return mvm_g<TV, TU, 32>(L, V, C, out, s, noise, p, partials);
+    default: return mvm_g<TV, TU, 64>(L, V, C, out, s, noise, p, partials);
+  }
 }
 
 }  // namespace
 
-int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s, float noise,
-             const float* p, double* partials) {
-  int rc = dev_reserve(const_cast<sgp_lattice*>(L)->ubuf, sizeof(float) * 4 * L->m * C);
-  if (rc) return rc;
-  switch (lanes_for(C)) {
-    case 1: return mvm_g<1>(L, V, C, out, s, noise, p, partials);
-    case 2: return mvm_g<2>(L, V, C, out, s, noise, p, partials);
-    case 4: return mvm_g<4>(L, V, C, out, s, noise, p, partials);
-    case 8: return mvm_g<8>(L, V, C, out, s, noise, p, partials);
-    case 16: return mvm_g<16>(L, V, C, out, s, noise, p, partials);
-    case 32: return mvm_g<32>(L, V, C, out, s, noise, p, partials);
-    default: return mvm_g<64>(L, V, C, out, s, noise, p, partials);
-  }
+int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s) {
+  return mvm_dispatch<float, float>(L, V, C, out, s, 0.f, nullptr, nullptr);
+}
+
+int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t s, double noise,
+           double* partials) {
+  return mvm_dispatch<double, double>(L, p, C, q, s, noise, p, partials);
 }
 
 }  // namespace sgp
@@ -245,5 +259,5 @@ extern "C" int lattice_mvm(const sgp_lattice* L, const float* values, int32_t C,
     set_error("lattice_mvm: out overlaps values");
     return SGP_EINVAL;
   }
-  return mvm_into(L, values, C, out, (hipStream_t)stream, 0.f, nullptr, nullptr);
+  return mvm_into(L, values, C, out, (hipStream_t)stream);
 }

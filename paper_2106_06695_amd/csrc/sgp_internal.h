@@ -48,6 +48,7 @@ enum KernelKind {
   KK_CG_SCALAR,
   KK_CG_UPDATE,
   KK_CG_DIR,
+  KK_CG_OUT,
   KK_NUM
 };
 
@@ -93,7 +94,7 @@ struct sgp_lattice {
   int64_t m = 0;
   int device = 0;
   double spacing = 0;
-  float stencil[2 * sgp::kMaxOrder + 1] = {};
+  double stencil64[2 * sgp::kMaxOrder + 1] = {};
 
   sgp::DevBuf idx;   // n x (d+1) int32
   sgp::DevBuf w;     // n x (d+1) fp32
@@ -109,10 +110,13 @@ struct sgp_lattice {
 namespace sgp {
 // Host-side constants (Section 4.1 and Section 3.2 Splat).
 int make_constants(int d, int r, int kernel, const double* ell, double* spacing,
-                   float* stencil, double* f);
+                   double* stencil, double* f);
 
 // Launchers used across files.
 int launch_fill_u32(uint32_t* p, size_t count, uint32_t value, hipStream_t s);
-int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s,
-             float noise, const float* p_for_noise, double* partials);
+// fp32 values, fp32 lattice accumulation (lattice_mvm)
+int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s);
+// fp64 values and accumulation with the CG epilogue: q = A p, partial sums of p.q
+int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t s, double noise,
+           double* partials);
 }  // namespace sgp
