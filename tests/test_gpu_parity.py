@@ -235,11 +235,22 @@ def test_ws2_full(sgp, orc):
     w = workloads.ws2()
     lat, olat = _build_both(sgp, orc, w.X, w.lengthscales)
     _assert_structure(sgp, lat, olat)
+    b = w.values.astype(np.float64)
     out = sgp.lattice_mvm(lat, _cuda(w.values)).cpu().numpy()
-    assert _colerr(out, olat.mvm(w.values.astype(np.float64))).max() <= MVM_TOL
-    x, iters, rel = sgp.cg_solve(lat, _cuda(w.values), w.noise, w.tol, max_iter=500)
-    xo, itero, relo, _ = olat.cg(w.values.astype(np.float64), w.noise, w.tol, max_iter=500)
-    assert rel[0] <= w.tol and abs(int(iters[0]) - int(itero[0])) <= 1
+    assert _colerr(out, olat.mvm(b)).max() <= MVM_TOL
+    # a few fixed iterations: iterate parity
+    x, iters, rel = sgp.cg_solve(lat, _cuda(w.values), w.noise, 0.0, max_iter=10)
+    xo, _, _, _ = olat.cg(b, w.noise, 0.0, max_iter=10)
+    assert _colerr(x.cpu().numpy(), xo).max() <= CG_TOL
+    # to the tolerance (cond ~2e5, hundreds of iterations): the GPU's answer
+    # meets the tolerance under the oracle's operator, in a similar count
+    x, iters, rel = sgp.cg_solve(lat, _cuda(w.values), w.noise, w.tol, max_iter=w.max_iter)
+    xo, itero, relo, _ = olat.cg(b, w.noise, w.tol, max_iter=w.max_iter)
+    assert rel[0] <= w.tol and relo[0] <= w.tol
+    assert abs(int(iters[0]) - int(itero[0])) <= 0.1 * itero[0], (iters, itero)
+    xg = x.cpu().numpy().astype(np.float64)
+    res = b - (olat.mvm(xg) + w.noise * xg)
+    assert np.linalg.norm(res) / np.linalg.norm(b) <= 1.05 * w.tol
 
 
 def test_ws3_full(sgp, orc):

@@ -10,7 +10,7 @@ which are not available here; every array is synthetic:
 
   ws1  n=2,000     d=3   X ~ N(0, I), l = 1, C = 1, noise 0.1, tol 1e-4
   ws2  n=500,000   d=8   mixture of 20 Gaussians, l ~ logU[0.5, 2], C = 1,
-                         noise 0.05, tol 1e-2
+                         noise 0.05, tol 1e-2 (up to 1,500 iterations)
   ws3  n=2,000,000 d=11  mixture of 50 Gaussians, l ~ logU[0.5, 2],
                          C = 16 (1 target ~ N(0,1) + 15 Rademacher probes),
                          noise 0.05, 20 fixed CG iterations
@@ -92,7 +92,10 @@ def ws2(seed: int = 1002, n: int = 500_000) -> Workload:
     X = mixture(rng, n, 8, 20)
     ell = log_uniform(rng, 0.5, 2.0, 8)
     V = rng.standard_normal((n, 1)).astype(np.float32)
-    return Workload("ws2", X, ell, V, noise=0.05, tol=1e-2, max_iter=500)
+    # the unpreconditioned solve needs ~540 iterations to reach 1e-2 here
+    # (cond(K + 0.05 I) ~ 2e5); the paper's cap of 500 goes with its
+    # pivoted-Cholesky preconditioner
+    return Workload("ws2", X, ell, V, noise=0.05, tol=1e-2, max_iter=1500)
 
 
 def ws3(seed: int = 1003, n: int = 2_000_000, channels: int = 16) -> Workload:
