@@ -33,8 +33,12 @@ struct CgState {
 
 enum ScalarMode { SM_START = 0, SM_ALPHA = 1, SM_BETA = 2 };
 
+// Vectors live in the lattice's internal point order: b is gathered through
+// the permutation here and x scattered back in k_cg_out.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b, double* __restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
+                                                    const uint32_t* __restrict__ perm,
+                                                    double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p,
                                                     int64_t n, int C, double* __restrict__ partials) {
   constexpr int R = kBlock / G;
@@ -44,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
   if (lane < C) {
     for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
       const int64_t e = i * C + lane;
-      const double v = (double)b[e];
+      const double v = (double)b[(int64_t)perm[i] * C + lane];
       x[e] = 0.0;
       r[e] = v;
       p[e] = v;
@@ -61,56 +65,72 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
   }
 }
 
-// Sum the kRedBlocks partials of each column in a fixed order and apply one
-// step of the scalar recurrence.
-__global__ __launch_bounds__(kBlock) void k_cg_scalar(const double* __restrict__ partials, int C,
-                                                      CgState* __restrict__ st, int mode, double tol) {
-  __shared__ double sh[kBlock];
+constexpr int kScalarThreads = 1024;
+
+// Sum the nparts partial rows of each column in a fixed order and apply one
+// step of the scalar recurrence. Thread (g, c) sums rows g, g + RG, ... of
+// column c (RG row groups, coalesced across c); one thread per column then
+// folds the RG group sums in order.
+__global__ __launch_bounds__(kScalarThreads) void k_cg_scalar(const double* __restrict__ partials,
+                                                              int64_t nparts, int C,
+                                                              CgState* __restrict__ st, int mode,
+                                                              double tol) {
+  __shared__ double sh[kScalarThreads];
   const int tid = threadIdx.x;
-  for (int c = 0; c < C; ++c) {
-    double s = 0.0;
-    for (int b = tid; b < kRedBlocks; b += kBlock) s += partials[(int64_t)b * C + c];
-    sh[tid] = s;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-      if (tid < off) sh[tid] += sh[tid + off];
-      __syncthreads();
+  const int RG = kScalarThreads / C;  // C <= 64, so RG >= 16
+  const int g = tid / C, c = tid - g * C;
+  double s = 0.0;
+  if (g < RG) {
+    int64_t b = g;
+    for (; b + 3 * RG < nparts; b += 4 * RG) {
+      const double a0 = partials[b * C + c];
+      const double a1 = partials[(b + RG) * C + c];
+      const double a2 = partials[(b + 2 * RG) * C + c];
+      const double a3 = partials[(b + 3 * RG) * C + c];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
     }
-    if (tid == 0) {
-      const double v = sh[0];
-      if (mode == SM_START) {
-        st->rr[c] = v;
-        st->bnorm[c] = sqrt(v);
-        st->active[c] = v > 0.0 ? 1 : 0;
-        st->iters[c] = 0;
-        st->rel[c] = v > 0.0 ? 1.f : 0.f;
-        st->alpha[c] = 0.0;
-        st->beta[c] = 0.0;
-      } else if (mode == SM_ALPHA) {
-        if (st->active[c] && v > 0.0) {
-          st->alpha[c] = st->rr[c] / v;
+    for (; b < nparts; b += RG) s += partials[b * C + c];
+  }
+  sh[tid] = s;
+  __syncthreads();
+  if (tid < C) {
+    double v = 0.0;
+    for (int gg = 0; gg < RG; ++gg) v += sh[gg * C + tid];
+    const int cc = tid;
+    if (mode == SM_START) {
+      st->rr[cc] = v;
+      st->bnorm[cc] = sqrt(v);
+      st->active[cc] = v > 0.0 ? 1 : 0;
+      st->iters[cc] = 0;
+      st->rel[cc] = v > 0.0 ? 1.f : 0.f;
+      st->alpha[cc] = 0.0;
+      st->beta[cc] = 0.0;
+    } else if (mode == SM_ALPHA) {
+      if (st->active[cc] && v > 0.0) {
+        st->alpha[cc] = st->rr[cc] / v;
+      } else {
+        st->alpha[cc] = 0.0;
+        st->active[cc] = 0;  // converged, or breakdown (p.Ap <= 0)
+      }
+    } else {
+      if (st->active[cc]) {
+        st->iters[cc] += 1;
+        const double rel = sqrt(v) / st->bnorm[cc];
+        st->rel[cc] = (float)rel;
+        if (rel <= tol) {
+          st->active[cc] = 0;
+          st->beta[cc] = 0.0;
         } else {
-          st->alpha[c] = 0.0;
-          st->active[c] = 0;  // converged, or breakdown (p.Ap <= 0)
+          st->beta[cc] = v / st->rr[cc];
+          st->rr[cc] = v;
         }
       } else {
-        if (st->active[c]) {
-          st->iters[c] += 1;
-          const double rel = sqrt(v) / st->bnorm[c];
-          st->rel[c] = (float)rel;
-          if (rel <= tol) {
-            st->active[c] = 0;
-            st->beta[c] = 0.0;
-          } else {
-            st->beta[c] = v / st->rr[c];
-            st->rr[c] = v;
-          }
-        } else {
-          st->beta[c] = 0.0;
-        }
+        st->beta[cc] = 0.0;
       }
     }
-    __syncthreads();
   }
 }
 
@@ -158,11 +178,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(const double* __restrict__ r,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_out(const double* __restrict__ x64, float* __restrict__ x,
-                                                   int64_t count) {
+__global__ __launch_bounds__(kBlock) void k_cg_out(const double* __restrict__ x64,
+                                                   const uint32_t* __restrict__ perm,
+                                                   float* __restrict__ x, int64_t count, int C) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride)
-    x[e] = (float)x64[e];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
+    const int64_t i = e / C;
+    const int c = (int)(e - i * C);
+    x[(int64_t)perm[i] * C + c] = (float)x64[e];
+  }
 }
 
 template <int G>
@@ -172,14 +196,16 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   const int64_t n = L->n, nC = n * C;
   int rc;
   if ((rc = dev_reserve(Lm->cgvec, sizeof(double) * 4 * nC))) return rc;
-  const size_t red_bytes = sizeof(double) * kRedBlocks * C + sizeof(CgState) + 256;
+  // partial sums: kRedBlocks rows from the vector kernels, one row per tile from the slice
+  const int64_t nparts = L->ntiles > kRedBlocks ? L->ntiles : kRedBlocks;
+  const size_t red_bytes = sizeof(double) * nparts * C + sizeof(CgState) + 256;
   if ((rc = dev_reserve(Lm->cgred, red_bytes))) return rc;
   double* x64 = (double*)Lm->cgvec.ptr;
   double* r = x64 + nC;
   double* p = r + nC;
   double* q = p + nC;
   double* partials = (double*)Lm->cgred.ptr;
-  CgState* st = (CgState*)((char*)Lm->cgred.ptr + ((sizeof(double) * kRedBlocks * C + 255) / 256) * 256);
+  CgState* st = (CgState*)((char*)Lm->cgred.ptr + ((sizeof(double) * nparts * C + 255) / 256) * 256);
 
   int32_t* host = nullptr;
   SGP_HIP(hipHostMalloc((void**)&host, sizeof(int32_t) * 3 * kMaxCgCols, hipHostMallocDefault));
@@ -191,12 +217,14 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   const dim3 grid(kRedBlocks), block(kBlock);
   {
     ProfScope ps(KK_CG_INIT, s);
-    hipLaunchKernelGGL(k_cg_init<G>, grid, block, 0, s, b, x64, r, p, n, C, partials);
+    hipLaunchKernelGGL(k_cg_init<G>, grid, block, 0, s, b, (const uint32_t*)L->perm.ptr, x64, r, p, n, C,
+                       partials);
     SGP_LAUNCH_CHECK("k_cg_init");
   }
   {
     ProfScope ps(KK_CG_SCALAR, s);
-    hipLaunchKernelGGL(k_cg_scalar, dim3(1), block, 0, s, partials, C, st, (int)SM_START, (double)tol);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, partials, (int64_t)kRedBlocks, C, st,
+                       (int)SM_START, (double)tol);
     SGP_LAUNCH_CHECK("k_cg_scalar");
   }
   // polling interval: each poll drains the queue, so poll less when the
@@ -206,7 +234,8 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     if ((rc = mvm_cg(L, p, C, q, s, (double)noise, partials))) return rc;
     {
       ProfScope ps(KK_CG_SCALAR, s);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), block, 0, s, partials, C, st, (int)SM_ALPHA, (double)tol);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, partials, L->ntiles, C, st,
+                         (int)SM_ALPHA, (double)tol);
       SGP_LAUNCH_CHECK("k_cg_scalar");
     }
     {
@@ -216,7 +245,8 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     }
     {
       ProfScope ps(KK_CG_SCALAR, s);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), block, 0, s, partials, C, st, (int)SM_BETA, (double)tol);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, partials, (int64_t)kRedBlocks, C, st,
+                         (int)SM_BETA, (double)tol);
       SGP_LAUNCH_CHECK("k_cg_scalar");
     }
     {
@@ -234,7 +264,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   }
   {
     ProfScope ps(KK_CG_OUT, s);
-    hipLaunchKernelGGL(k_cg_out, dim3(kRedBlocks), block, 0, s, x64, x, nC);
+    hipLaunchKernelGGL(k_cg_out, dim3(kRedBlocks), block, 0, s, x64, (const uint32_t*)L->perm.ptr, x, nC, C);
     SGP_LAUNCH_CHECK("k_cg_out");
   }
   SGP_HIP(hipMemcpyAsync(host, st->iters, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -12,6 +13,27 @@ namespace sgp {
 
 namespace {
 thread_local char g_err[512] = "";
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  char* end = nullptr;
+  const long x = std::strtol(v, &end, 10);
+  return (end && *end == 0) ? (int)x : dflt;
+}
+}  // namespace
+
+const Tuning& tuning() {
+  static const Tuning t = [] {
+    Tuning k;
+    k.lds_budget = env_int("SGP_LDS_BUDGET", 65536);
+    if (k.lds_budget < 8192) k.lds_budget = 8192;
+    if (k.lds_budget > 65536) k.lds_budget = 65536;
+    k.slice_rows = env_int("SGP_SLICE_ROWS", 128);
+    k.splat_stage_v = env_int("SGP_SPLAT_STAGE_V", 1);
+    return k;
+  }();
+  return t;
 }
 
 void set_error(const char* fmt, ...) {
@@ -73,7 +95,7 @@ int64_t g_prof_launches[KK_NUM] = {};
 double g_prof_ms[KK_NUM] = {};
 const char* const kKindNames[KK_NUM] = {
     "fill", "simplex_insert", "count_first", "scan", "compact", "resolve", "neighbors",
-    "splat", "blur", "slice", "cg_init", "cg_scalar", "cg_update", "cg_dir", "cg_out"};
+    "splat", "splat_gather", "blur", "slice", "cg_init", "cg_scalar", "cg_update", "cg_dir", "cg_out", "sort", "order"};
 
 // Fold completed records into the totals. Caller holds the mutex.
 int prof_drain() {
@@ -212,8 +234,10 @@ int lattice_info(const sgp_lattice* L, int64_t* n, int32_t* d, int64_t* m, int64
   if (d) *d = L->d;
   if (m) *m = L->m;
   if (device_bytes)
-    *device_bytes = (int64_t)(L->idx.bytes + L->w.bytes + L->keys.bytes + L->nbr.bytes +
-                              L->ubuf.bytes + L->cgvec.bytes + L->cgred.bytes);
+    *device_bytes = (int64_t)(L->perm.bytes + L->loc.bytes + L->ws.bytes + L->tile_off.bytes +
+                              L->tile_verts.bytes + L->run_rel.bytes + L->ent_lp.bytes + L->ent_w.bytes +
+                              L->occ_ptr.bytes + L->occ.bytes + L->nbr.bytes + L->int2can.bytes +
+                              L->keys.bytes + L->ubuf.bytes + L->cgvec.bytes + L->cgred.bytes);
   return SGP_OK;
 }
 
@@ -225,17 +249,45 @@ int lattice_export(const sgp_lattice* L, int32_t* keys, int32_t* idx, float* w, 
   SGP_HIP(hipSetDevice(L->device));
   SGP_HIP(hipDeviceSynchronize());
   const int D = L->d + 1, T = 2 * L->order;
-  if (keys && L->m) SGP_HIP(hipMemcpy(keys, L->keys.ptr, sizeof(int32_t) * L->m * L->d, hipMemcpyDeviceToHost));
-  if (idx) SGP_HIP(hipMemcpy(idx, L->idx.ptr, sizeof(int32_t) * L->n * D, hipMemcpyDeviceToHost));
-  if (w) SGP_HIP(hipMemcpy(w, L->w.ptr, sizeof(float) * L->n * D, hipMemcpyDeviceToHost));
-  if (nbr && L->m) {
-    // device layout [direction][offset][point] -> [point][direction][offset]
-    std::vector<int32_t> tmp((size_t)D * T * L->m);
+  const int64_t n = L->n, m = L->m;
+  if (keys) SGP_HIP(hipMemcpy(keys, L->keys.ptr, sizeof(int32_t) * m * L->d, hipMemcpyDeviceToHost));
+  std::vector<int32_t> int2can;
+  if (idx || nbr) {
+    int2can.resize(m);
+    SGP_HIP(hipMemcpy(int2can.data(), L->int2can.ptr, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  }
+  if (idx || w) {
+    // internal (sorted point, tile run) -> caller's point order, canonical vertex
+    const int P = L->tile_points;
+    std::vector<uint32_t> perm(n);
+    std::vector<uint16_t> loc((size_t)n * D);
+    std::vector<float> ws((size_t)n * D);
+    std::vector<int32_t> toff(L->ntiles + 1), tverts(L->nrun);
+    SGP_HIP(hipMemcpy(perm.data(), L->perm.ptr, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    SGP_HIP(hipMemcpy(loc.data(), L->loc.ptr, sizeof(uint16_t) * n * D, hipMemcpyDeviceToHost));
+    SGP_HIP(hipMemcpy(ws.data(), L->ws.ptr, sizeof(float) * n * D, hipMemcpyDeviceToHost));
+    SGP_HIP(hipMemcpy(toff.data(), L->tile_off.ptr, sizeof(int32_t) * toff.size(), hipMemcpyDeviceToHost));
+    SGP_HIP(hipMemcpy(tverts.data(), L->tile_verts.ptr, sizeof(int32_t) * tverts.size(),
+                      hipMemcpyDeviceToHost));
+    for (int64_t ip = 0; ip < n; ++ip) {
+      const int64_t i = perm[ip];
+      const int32_t base = toff[ip / P];
+      for (int k = 0; k < D; ++k) {
+        if (idx) idx[i * D + k] = int2can[tverts[base + loc[ip * D + k]]];
+        if (w) w[i * D + k] = ws[ip * D + k];
+      }
+    }
+  }
+  if (nbr) {
+    // device layout [direction][offset][internal point] -> [canonical point][direction][offset]
+    std::vector<int32_t> tmp((size_t)D * T * m);
     SGP_HIP(hipMemcpy(tmp.data(), L->nbr.ptr, sizeof(int32_t) * tmp.size(), hipMemcpyDeviceToHost));
     for (int k = 0; k < D; ++k)
       for (int t = 0; t < T; ++t)
-        for (int64_t j = 0; j < L->m; ++j)
-          nbr[((size_t)j * D + k) * T + t] = tmp[((size_t)k * T + t) * L->m + j];
+        for (int64_t ji = 0; ji < m; ++ji) {
+          const int32_t v = tmp[((size_t)k * T + t) * m + ji];
+          nbr[((size_t)int2can[ji] * D + k) * T + t] = v >= 0 ? int2can[v] : -1;
+        }
   }
   return SGP_OK;
 }
@@ -244,10 +296,9 @@ void lattice_free(sgp_lattice* L) {
   if (!L) return;
   (void)hipSetDevice(L->device);
   (void)hipDeviceSynchronize();
-  dev_free(L->idx);
-  dev_free(L->w);
-  dev_free(L->keys);
-  dev_free(L->nbr);
+  for (DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->tile_verts, &L->run_rel,
+                   &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->occ, &L->nbr, &L->int2can, &L->keys})
+    dev_free(*b);
   dev_free(L->ubuf);
   dev_free(L->cgvec);
   dev_free(L->cgred);

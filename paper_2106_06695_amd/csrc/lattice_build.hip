@@ -15,8 +15,10 @@
 // hashes would share a slot; k_resolve compares every vertex key with the
 // stored key of its slot and the host rebuilds with a new seed if any
 // differ, so the final lattice is exact.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "sgp_internal.h"
 
@@ -70,6 +72,8 @@ struct SimplexArgs {
   unsigned long long mask;
   unsigned long long seed;
   uint32_t* flags;
+  int32_t* rmin;  // per-dimension min / max of the remainder-0 point, in units of d+1
+  int32_t* rmax;
 };
 
 // Returns the slot of hash h, claiming an empty one if needed; -1 if full.
@@ -176,7 +180,21 @@ __global__ __launch_bounds__(kBlock) void k_simplex_insert(SimplexArgs a) {
   if (ok) sh_q[base + rank] = del / (double)D;
   sh_i[tid] = r0;
   sh_rk[tid] = rank;
+  __shared__ int32_t sh_min[kMaxD], sh_max[kMaxD];
+  if (tid < d) {
+    sh_min[tid] = INT32_MAX;
+    sh_max[tid] = INT32_MIN;
+  }
   __syncthreads();
+  if (ok && j < d) {
+    atomicMin(&sh_min[j], r0 / D);
+    atomicMax(&sh_max[j], r0 / D);
+  }
+  __syncthreads();
+  if (tid < d && sh_min[tid] <= sh_max[tid]) {
+    atomicMin(&a.rmin[tid], sh_min[tid]);
+    atomicMax(&a.rmax[tid], sh_max[tid]);
+  }
   if (!ok) {
     if (live) a.slot[i * D + j] = -1;  // rejected point: later passes skip its vertices
     return;
@@ -379,6 +397,226 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict_
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Internal order. Points are sorted by their remainder-0 lattice point
+// (coordinates in units of d+1, packed most-significant-first into 64 bits)
+// so that a block of consecutive points touches few distinct lattice points;
+// lattice points are then renumbered by first touch in that order, and W^T
+// is stored as a CSR over those numbers so that the splat is a gather.
+
+struct KeyPack {
+  int32_t lo[kMaxD];
+  int32_t shift[kMaxD];
+  int nk;  // leading dimensions packed into the key
+};
+
+__global__ __launch_bounds__(kBlock) void k_point_key(const int32_t* __restrict__ pt_r0, int64_t n, int d,
+                                                      KeyPack kp, unsigned long long* __restrict__ key,
+                                                      uint32_t* __restrict__ val) {
+  const int D = d + 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    unsigned long long k = 0;
+    for (int l = 0; l < kp.nk; ++l)
+      k |= (unsigned long long)(uint32_t)(pt_r0[i * d + l] / D - kp.lo[l]) << kp.shift[l];
+    key[i] = k;
+    val[i] = (uint32_t)i;
+  }
+}
+
+// Slot of every (sorted point, vertex) element and first touch per slot.
+__global__ __launch_bounds__(kBlock) void k_first_touch(const uint32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ slot, int64_t L,
+                                                        int D, int32_t* __restrict__ slot_s,
+                                                        uint32_t* __restrict__ first2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += stride) {
+    const int64_t ip = e / D;
+    const int k = (int)(e - ip * D);
+    const int32_t s = slot[(int64_t)perm[ip] * D + k];
+    slot_s[e] = s;
+    if (__hip_atomic_load(&first2[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (uint32_t)e)
+      atomicMin(&first2[s], (uint32_t)e);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_internal(const int32_t* __restrict__ slot_s,
+                                                             uint32_t* __restrict__ first2, int64_t L,
+                                                             const uint32_t* __restrict__ offsets,
+                                                             const uint32_t* __restrict__ tab_first,
+                                                             int64_t m, int32_t* __restrict__ int2can,
+                                                             uint32_t* __restrict__ flags) {
+  const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
+  bool flag[kItems];
+  int c = 0;
+  for (int u = 0; u < kItems; ++u) {
+    const int64_t e = base + u;
+    flag[u] = e < L && is_first(slot_s, first2, e);
+    c += flag[u] ? 1 : 0;
+  }
+  int total;
+  uint32_t pos = offsets[blockIdx.x] + (uint32_t)block_exclusive_scan(c, &total);
+  for (int u = 0; u < kItems; ++u) {
+    if (!flag[u]) continue;
+    if ((int64_t)pos >= m) {
+      atomicOr(flags, BF_COLLISION);
+      break;
+    }
+    const int32_t sl = slot_s[base + u];
+    int2can[pos] = (int32_t)(tab_first[sl] & ~kCanonBit);
+    first2[sl] = kCanonBit | pos;
+    ++pos;
+  }
+}
+
+// (internal vertex, weight) of every (sorted point, vertex) element.
+__global__ __launch_bounds__(kBlock) void k_resolve_internal(const int32_t* __restrict__ slot_s,
+                                                             const uint32_t* __restrict__ first2,
+                                                             const uint32_t* __restrict__ perm,
+                                                             const float* __restrict__ w_orig,
+                                                             int64_t L, int D, int64_t m,
+                                                             sgp_entry* __restrict__ pm,
+                                                             uint32_t* __restrict__ flags) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += stride) {
+    const uint32_t v = first2[slot_s[e]];
+    int32_t j = (int32_t)(v & ~kCanonBit);
+    if (!(v & kCanonBit) || j >= m) {
+      atomicOr(flags, BF_COLLISION);
+      j = 0;
+    }
+    const int64_t ip = e / D;
+    const int k = (int)(e - ip * D);
+    sgp_entry en;
+    en.j = j;
+    en.w = w_orig[(int64_t)perm[ip] * D + k];
+    pm[e] = en;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_can2int(const int32_t* __restrict__ int2can, int64_t m,
+                                                    int32_t* __restrict__ can2int) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride)
+    can2int[int2can[j]] = (int32_t)j;
+}
+
+// Neighbour table in internal numbering: rows and entries both mapped.
+__global__ __launch_bounds__(kBlock) void k_nbr_internal(const int32_t* __restrict__ nbr_can,
+                                                         const int32_t* __restrict__ int2can,
+                                                         const int32_t* __restrict__ can2int,
+                                                         int64_t m, int64_t lists,
+                                                         int32_t* __restrict__ nbr_int) {
+  const int64_t total = lists * m;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+    const int64_t list = g / m;
+    const int64_t j = g - list * m;
+    const int32_t nb = nbr_can[list * m + int2can[j]];
+    nbr_int[g] = nb >= 0 ? can2int[nb] : -1;
+  }
+}
+
+// Tiles: key = (tile of the sorted point, internal vertex); after a stable
+// sort by key, equal keys form a "run" = one lattice point of one tile, with
+// its entries in sorted-point order.
+__global__ __launch_bounds__(kBlock) void k_tile_keys(const sgp_entry* __restrict__ pm, int64_t L,
+                                                      int D, int P, int mb,
+                                                      unsigned long long* __restrict__ key,
+                                                      uint32_t* __restrict__ val) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += stride) {
+    const unsigned long long tile = (unsigned long long)((e / D) / P);
+    key[e] = (tile << mb) | (unsigned long long)(uint32_t)pm[e].j;
+    val[e] = (uint32_t)e;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_run_flags(const unsigned long long* __restrict__ key,
+                                                      int64_t L, uint32_t* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride)
+    flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1u : 0u;
+}
+
+// Run q of sorted entry p is (exclusive count of run starts before p) +
+// flag - 1. Entry p is the (p - tile * P * D)-th entry of its tile, since a
+// tile's entries are exactly those of its points. Writes the run lists (run
+// start relative to the tile, lattice point), the per-entry (point within
+// the tile, weight) in run order, and the tile offsets.
+__global__ __launch_bounds__(kBlock) void k_run_fill(const unsigned long long* __restrict__ key,
+                                                     const uint32_t* __restrict__ val,
+                                                     const uint32_t* __restrict__ flag,
+                                                     const uint32_t* __restrict__ ex,
+                                                     const sgp_entry* __restrict__ pm, int64_t L,
+                                                     int D, int P, int mb, int64_t ntiles,
+                                                     int32_t* __restrict__ tile_verts,
+                                                     uint16_t* __restrict__ run_rel,
+                                                     uint8_t* __restrict__ ent_lp,
+                                                     float* __restrict__ ent_w,
+                                                     int32_t* __restrict__ tile_off) {
+  const unsigned long long jmask = (1ull << mb) - 1ull;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride) {
+    const unsigned long long k = key[p];
+    const uint32_t e = val[p];
+    const uint32_t f = flag[p];
+    const int64_t q = (int64_t)ex[p] + f - 1;
+    const int64_t tile = (int64_t)(k >> mb);
+    ent_lp[p] = (uint8_t)((int64_t)(e / (uint32_t)D) - tile * P);
+    ent_w[p] = pm[e].w;
+    if (f) {
+      tile_verts[q] = (int32_t)(k & jmask);
+      run_rel[q] = (uint16_t)(p - tile * (int64_t)P * D);
+      if (p == 0 || (key[p - 1] >> mb) != (unsigned long long)tile) tile_off[tile] = (int32_t)q;
+    }
+    if (p == L - 1) tile_off[ntiles] = (int32_t)(q + 1);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_loc_fill(const unsigned long long* __restrict__ key,
+                                                     const uint32_t* __restrict__ val,
+                                                     const uint32_t* __restrict__ flag,
+                                                     const uint32_t* __restrict__ ex,
+                                                     const int32_t* __restrict__ tile_off,
+                                                     const sgp_entry* __restrict__ pm, int64_t L,
+                                                     int mb, uint16_t* __restrict__ loc,
+                                                     float* __restrict__ ws) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride) {
+    const int64_t q = (int64_t)ex[p] + flag[p] - 1;
+    const int64_t tile = (int64_t)(key[p] >> mb);
+    const uint32_t e = val[p];
+    loc[e] = (uint16_t)(q - tile_off[tile]);
+    ws[e] = pm[e].w;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_occ_keys(const int32_t* __restrict__ tile_verts, int64_t Q,
+                                                     uint32_t* __restrict__ key,
+                                                     uint32_t* __restrict__ val) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < Q; q += stride) {
+    key[q] = (uint32_t)tile_verts[q];
+    val[q] = (uint32_t)q;
+  }
+}
+
+// Runs sorted by lattice point: start of each point's list.
+__global__ __launch_bounds__(kBlock) void k_occ_fill(const uint32_t* __restrict__ key,
+                                                     const uint32_t* __restrict__ val, int64_t Q,
+                                                     int64_t m, int32_t* __restrict__ occ_ptr,
+                                                     int32_t* __restrict__ occ) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < Q; o += stride) {
+    const uint32_t j = key[o];
+    occ[o] = (int32_t)val[o];
+    if (o == 0 || key[o - 1] != j) occ_ptr[j] = (int32_t)o;
+    if (o == Q - 1) occ_ptr[m] = (int32_t)Q;
+  }
+}
+
 unsigned grid_for(int64_t work, int64_t per_block, int64_t cap) {
   int64_t b = (work + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -387,7 +625,8 @@ unsigned grid_for(int64_t work, int64_t per_block, int64_t cap) {
 }
 
 struct Transient {
-  void* ptr[8] = {};
+  static constexpr int kSlots = 20;
+  void* ptr[kSlots] = {};
   hipStream_t s = nullptr;
   int alloc(int slot_i, size_t bytes) {
     hipError_t e = hipMallocAsync(&ptr[slot_i], bytes ? bytes : 16, s);
@@ -404,6 +643,12 @@ struct Transient {
       if (p) (void)hipFreeAsync(p, s);
   }
 };
+
+int bits_for(uint64_t range) {  // bits to hold values 0..range
+  int b = 0;
+  while (b < 64 && (range >> b) != 0) ++b;
+  return b;
+}
 
 int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_factor,
                   unsigned long long seed, hipStream_t st, uint32_t* host_word, bool* retry) {
@@ -423,7 +668,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   Transient tr;
   tr.s = st;
   int rc;
-  enum { T_R0, T_RANK, T_SLOT, T_TAB, T_FIRST, T_COUNTS, T_OFFS, T_WORDS };
+  enum {
+    T_R0, T_RANK, T_SLOT, T_TAB, T_FIRST, T_COUNTS, T_OFFS, T_WORDS, T_IDX, T_W, T_NBRC,
+    T_SLOTS, T_FIRST2, T_CAN2INT, T_KA, T_KB, T_VA, T_VB, T_SORTTMP, T_PM
+  };
   if ((rc = tr.alloc(T_R0, sizeof(int32_t) * n * d))) return rc;
   if ((rc = tr.alloc(T_RANK, sizeof(uint8_t) * n * d))) return rc;
   if ((rc = tr.alloc(T_SLOT, sizeof(int32_t) * Lel))) return rc;
@@ -431,7 +679,9 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   if ((rc = tr.alloc(T_FIRST, sizeof(uint32_t) * cap))) return rc;
   if ((rc = tr.alloc(T_COUNTS, sizeof(uint32_t) * nb))) return rc;
   if ((rc = tr.alloc(T_OFFS, sizeof(uint32_t) * nb))) return rc;
-  if ((rc = tr.alloc(T_WORDS, sizeof(uint32_t) * 4))) return rc;
+  if ((rc = tr.alloc(T_WORDS, sizeof(uint32_t) * (4 + 2 * kMaxD)))) return rc;
+  if ((rc = tr.alloc(T_IDX, sizeof(int32_t) * Lel))) return rc;
+  if ((rc = tr.alloc(T_W, sizeof(float) * Lel))) return rc;
   int32_t* pt_r0 = (int32_t*)tr.ptr[T_R0];
   uint8_t* pt_rank = (uint8_t*)tr.ptr[T_RANK];
   int32_t* slot = (int32_t*)tr.ptr[T_SLOT];
@@ -439,18 +689,24 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   uint32_t* tab_first = (uint32_t*)tr.ptr[T_FIRST];
   uint32_t* counts = (uint32_t*)tr.ptr[T_COUNTS];
   uint32_t* offs = (uint32_t*)tr.ptr[T_OFFS];
-  uint32_t* words = (uint32_t*)tr.ptr[T_WORDS];  // [0] flags, [1] m
+  uint32_t* words = (uint32_t*)tr.ptr[T_WORDS];  // [0] flags, [1] m, [2] m again, [4..] min/max
+  int32_t* idx_orig = (int32_t*)tr.ptr[T_IDX];
+  float* w_orig = (float*)tr.ptr[T_W];
+  int32_t* rmin = (int32_t*)(words + 4);
+  int32_t* rmax = rmin + kMaxD;
 
   if ((rc = launch_fill_u32((uint32_t*)tab, (size_t)cap * 2, 0u, st))) return rc;
   if ((rc = launch_fill_u32(tab_first, (size_t)cap, kNoFirst, st))) return rc;
   if ((rc = launch_fill_u32(words, 4, 0u, st))) return rc;
+  if ((rc = launch_fill_u32((uint32_t*)rmin, kMaxD, 0x7fffffffu, st))) return rc;
+  if ((rc = launch_fill_u32((uint32_t*)rmax, kMaxD, 0x80000000u, st))) return rc;
 
   SimplexArgs a;
   a.X = X;
   a.n = n;
   a.d = d;
   for (int j = 0; j < kMaxD; ++j) a.f[j] = j < d ? f[j] : 0.0;
-  a.w = (float*)L->w.ptr;
+  a.w = w_orig;
   a.pt_r0 = pt_r0;
   a.pt_rank = pt_rank;
   a.slot = slot;
@@ -459,6 +715,8 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   a.mask = (unsigned long long)(cap - 1);
   a.seed = seed;
   a.flags = words;
+  a.rmin = rmin;
+  a.rmax = rmax;
   const int P = kBlock / D;
   {
     ProfScope ps(KK_SIMPLEX, st);
@@ -476,7 +734,8 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, counts, offs, nb, words + 1);
     SGP_LAUNCH_CHECK("k_scan");
   }
-  SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, st));
+  const size_t nwords = 4 + 2 * kMaxD;
+  SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * nwords, hipMemcpyDeviceToHost, st));
   SGP_HIP(hipStreamSynchronize(st));
   const uint32_t flags = host_word[0];
   const int64_t m = host_word[1];
@@ -496,11 +755,34 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     set_error("lattice_build: inconsistent lattice size %lld", (long long)m);
     return SGP_EHASH;
   }
+  // sort key: remainder-0 coordinates, leading dimensions first, as many as fit in 64 bits
+  KeyPack kp;
+  int key_bits = 0;
+  {
+    const int32_t* hmin = (const int32_t*)(host_word + 4);
+    const int32_t* hmax = hmin + kMaxD;
+    int nk = 0, used = 0, bl[kMaxD];
+    for (int l = 0; l < d; ++l) {
+      const int b = bits_for((uint64_t)((int64_t)hmax[l] - (int64_t)hmin[l]));
+      if (used + b > 64) break;
+      bl[l] = b;
+      used += b;
+      nk = l + 1;
+    }
+    int sh = used;
+    for (int l = 0; l < nk; ++l) {
+      sh -= bl[l];
+      kp.lo[l] = hmin[l];
+      kp.shift[l] = sh;
+    }
+    kp.nk = nk;
+    key_bits = used;
+  }
   L->m = m;
   dev_free(L->keys);
-  dev_free(L->nbr);
   if ((rc = dev_alloc(L->keys, sizeof(int32_t) * m * d))) return rc;
-  if ((rc = dev_alloc(L->nbr, sizeof(int32_t) * m * D * T))) return rc;
+  if ((rc = tr.alloc(T_NBRC, sizeof(int32_t) * m * D * T))) return rc;
+  int32_t* nbr_can = (int32_t*)tr.ptr[T_NBRC];
   {
     ProfScope ps(KK_COMPACT, st);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel, offs,
@@ -511,19 +793,185 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     ProfScope ps(KK_RESOLVE, st);
     hipLaunchKernelGGL(k_resolve, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, slot,
                        tab_first, Lel, pt_r0, pt_rank, d, (const int32_t*)L->keys.ptr, m,
-                       (int32_t*)L->idx.ptr, words);
+                       idx_orig, words);
     SGP_LAUNCH_CHECK("k_resolve");
   }
   {
     ProfScope ps(KK_NEIGHBORS, st);
     hipLaunchKernelGGL(k_neighbors, dim3(grid_for(m * D, kBlock, 16384)), dim3(kBlock), 0, st,
                        (const int32_t*)L->keys.ptr, m, d, L->order, tab, tab_first,
-                       (unsigned long long)(cap - 1), seed, (int32_t*)L->nbr.ptr);
+                       (unsigned long long)(cap - 1), seed, nbr_can);
     SGP_LAUNCH_CHECK("k_neighbors");
   }
-  SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+
+  // ---- internal order: sort points, renumber vertices by first touch
+  if ((rc = tr.alloc(T_SLOTS, sizeof(int32_t) * Lel))) return rc;
+  if ((rc = tr.alloc(T_FIRST2, sizeof(uint32_t) * cap))) return rc;
+  if ((rc = tr.alloc(T_CAN2INT, sizeof(int32_t) * m))) return rc;
+  if ((rc = tr.alloc(T_KA, sizeof(unsigned long long) * Lel))) return rc;
+  if ((rc = tr.alloc(T_KB, sizeof(unsigned long long) * Lel))) return rc;
+  if ((rc = tr.alloc(T_PM, sizeof(sgp_entry) * Lel))) return rc;
+  if ((rc = tr.alloc(T_VA, sizeof(uint32_t) * Lel))) return rc;
+  if ((rc = tr.alloc(T_VB, sizeof(uint32_t) * Lel))) return rc;
+  if ((rc = tr.alloc(T_SORTTMP, sizeof(uint32_t) * radix_tmp_words(Lel)))) return rc;
+  int32_t* slot_s = (int32_t*)tr.ptr[T_SLOTS];
+  uint32_t* first2 = (uint32_t*)tr.ptr[T_FIRST2];
+  int32_t* can2int = (int32_t*)tr.ptr[T_CAN2INT];
+  uint32_t* va = (uint32_t*)tr.ptr[T_VA];
+  uint32_t* vb = (uint32_t*)tr.ptr[T_VB];
+  uint32_t* sort_tmp = (uint32_t*)tr.ptr[T_SORTTMP];
+  for (sgp::DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->tile_verts, &L->run_rel,
+                         &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->occ, &L->nbr, &L->int2can})
+    dev_free(*b);
+  if ((rc = dev_alloc(L->perm, sizeof(uint32_t) * n))) return rc;
+  if ((rc = dev_alloc(L->loc, sizeof(uint16_t) * Lel))) return rc;
+  if ((rc = dev_alloc(L->ws, sizeof(float) * Lel))) return rc;
+  if ((rc = dev_alloc(L->nbr, sizeof(int32_t) * m * D * T))) return rc;
+  if ((rc = dev_alloc(L->int2can, sizeof(int32_t) * m))) return rc;
+  sgp_entry* pm = (sgp_entry*)tr.ptr[T_PM];
+  uint32_t* perm = (uint32_t*)L->perm.ptr;
+  {
+    unsigned long long* ka = (unsigned long long*)tr.ptr[T_KA];
+    unsigned long long* kb = (unsigned long long*)tr.ptr[T_KB];
+    {
+      ProfScope ps(KK_ORDER, st);
+      hipLaunchKernelGGL(k_point_key, dim3(grid_for(n, kBlock, 16384)), dim3(kBlock), 0, st, pt_r0, n,
+                         d, kp, ka, va);
+      SGP_LAUNCH_CHECK("k_point_key");
+    }
+    bool in_alt = false;
+    if ((rc = radix_sort_pairs<unsigned long long>(ka, va, kb, vb, n, key_bits, sort_tmp, st, &in_alt)))
+      return rc;
+    SGP_HIP(hipMemcpyAsync(perm, in_alt ? vb : va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+  }
+  if ((rc = launch_fill_u32(first2, (size_t)cap, kNoFirst, st))) return rc;
+  {
+    ProfScope ps(KK_ORDER, st);
+    hipLaunchKernelGGL(k_first_touch, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, perm,
+                       slot, Lel, D, slot_s, first2);
+    SGP_LAUNCH_CHECK("k_first_touch");
+  }
+  {
+    ProfScope ps(KK_COUNT, st);
+    hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, slot_s, first2, Lel,
+                       counts);
+    SGP_LAUNCH_CHECK("k_count_first");
+  }
+  {
+    ProfScope ps(KK_SCAN, st);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, counts, offs, nb, words + 2);
+    SGP_LAUNCH_CHECK("k_scan");
+  }
+  {
+    ProfScope ps(KK_ORDER, st);
+    hipLaunchKernelGGL(k_compact_internal, dim3((unsigned)nb), dim3(kBlock), 0, st, slot_s, first2, Lel,
+                       offs, tab_first, m, (int32_t*)L->int2can.ptr, words);
+    SGP_LAUNCH_CHECK("k_compact_internal");
+    hipLaunchKernelGGL(k_resolve_internal, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st,
+                       slot_s, first2, perm, w_orig, Lel, D, m, pm, words);
+    SGP_LAUNCH_CHECK("k_resolve_internal");
+    hipLaunchKernelGGL(k_can2int, dim3(grid_for(m, kBlock, 16384)), dim3(kBlock), 0, st,
+                       (const int32_t*)L->int2can.ptr, m, can2int);
+    SGP_LAUNCH_CHECK("k_can2int");
+    hipLaunchKernelGGL(k_nbr_internal, dim3(grid_for(m * D * T, kBlock, 16384)), dim3(kBlock), 0, st,
+                       nbr_can, (const int32_t*)L->int2can.ptr, can2int, m, (int64_t)D * T,
+                       (int32_t*)L->nbr.ptr);
+    SGP_LAUNCH_CHECK("k_nbr_internal");
+  }
+  // ---- tiles of consecutive sorted points, their runs, and runs per lattice point
+  {
+    // tile size: at most 256 points (a point index fits 8 bits) and 4096
+    // entries (the tile kernels stage a tile's entries in LDS)
+    const int P = std::min(256, 4096 / D);
+    L->tile_points = P;
+    const int64_t ntiles = (n + P - 1) / P;
+    L->ntiles = ntiles;
+    const int mb = bits_for((uint64_t)(m - 1));
+    const int tb = bits_for((uint64_t)(ntiles - 1));
+    unsigned long long* ka = (unsigned long long*)tr.ptr[T_KA];
+    unsigned long long* kb = (unsigned long long*)tr.ptr[T_KB];
+    {
+      ProfScope ps(KK_ORDER, st);
+      hipLaunchKernelGGL(k_tile_keys, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st,
+                         (const sgp_entry*)tr.ptr[T_PM], Lel, D, P, mb, ka, va);
+      SGP_LAUNCH_CHECK("k_tile_keys");
+    }
+    bool in_alt = false;
+    if ((rc = radix_sort_pairs<unsigned long long>(ka, va, kb, vb, Lel, mb + tb, sort_tmp, st, &in_alt)))
+      return rc;
+    const unsigned long long* sk = in_alt ? kb : ka;
+    const uint32_t* sv = in_alt ? vb : va;
+    uint32_t* flag = (uint32_t*)(in_alt ? ka : kb);  // the other key buffer: 2 x Lel words
+    uint32_t* ex = flag + Lel;
+    {
+      ProfScope ps(KK_ORDER, st);
+      hipLaunchKernelGGL(k_run_flags, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, Lel,
+                         flag);
+      SGP_LAUNCH_CHECK("k_run_flags");
+    }
+    if ((rc = scan_exclusive_u32(flag, ex, Lel, words + 3, sort_tmp, st))) return rc;
+    SGP_HIP(hipMemcpyAsync(host_word + 3, words + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SGP_HIP(hipStreamSynchronize(st));
+    const int64_t Q = host_word[3];
+    if (Q < 1 || Q > Lel) {
+      set_error("lattice_build: inconsistent tile run count %lld", (long long)Q);
+      return SGP_EHASH;
+    }
+    L->nrun = Q;
+    if ((rc = dev_alloc(L->tile_off, sizeof(int32_t) * (ntiles + 1)))) return rc;
+    if ((rc = dev_alloc(L->tile_verts, sizeof(int32_t) * Q))) return rc;
+    if ((rc = dev_alloc(L->run_rel, sizeof(uint16_t) * Q))) return rc;
+    if ((rc = dev_alloc(L->ent_lp, sizeof(uint8_t) * Lel))) return rc;
+    if ((rc = dev_alloc(L->ent_w, sizeof(float) * Lel))) return rc;
+    if ((rc = dev_alloc(L->occ_ptr, sizeof(int32_t) * (m + 1)))) return rc;
+    if ((rc = dev_alloc(L->occ, sizeof(int32_t) * Q))) return rc;
+    {
+      ProfScope ps(KK_ORDER, st);
+      hipLaunchKernelGGL(k_run_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, sv,
+                         flag, ex, (const sgp_entry*)tr.ptr[T_PM], Lel, D, P, mb, ntiles,
+                         (int32_t*)L->tile_verts.ptr, (uint16_t*)L->run_rel.ptr,
+                         (uint8_t*)L->ent_lp.ptr, (float*)L->ent_w.ptr, (int32_t*)L->tile_off.ptr);
+      SGP_LAUNCH_CHECK("k_run_fill");
+      hipLaunchKernelGGL(k_loc_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, sv,
+                         flag, ex, (const int32_t*)L->tile_off.ptr, (const sgp_entry*)tr.ptr[T_PM],
+                         Lel, mb, (uint16_t*)L->loc.ptr, (float*)L->ws.ptr);
+      SGP_LAUNCH_CHECK("k_loc_fill");
+    }
+    // runs grouped by lattice point (32-bit keys; reuses the sort buffers)
+    uint32_t* k32a = (uint32_t*)(in_alt ? kb : ka);
+    uint32_t* k32b = k32a + Q;
+    {
+      ProfScope ps(KK_ORDER, st);
+      hipLaunchKernelGGL(k_occ_keys, dim3(grid_for(Q, kBlock, 16384)), dim3(kBlock), 0, st,
+                         (const int32_t*)L->tile_verts.ptr, Q, k32a, va);
+      SGP_LAUNCH_CHECK("k_occ_keys");
+    }
+    bool occ_alt = false;
+    if ((rc = radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, Q, mb, sort_tmp, st, &occ_alt))) return rc;
+    {
+      ProfScope ps(KK_ORDER, st);
+      hipLaunchKernelGGL(k_occ_fill, dim3(grid_for(Q, kBlock, 16384)), dim3(kBlock), 0, st,
+                         occ_alt ? k32b : k32a, occ_alt ? vb : va, Q, m, (int32_t*)L->occ_ptr.ptr,
+                         (int32_t*)L->occ.ptr);
+      SGP_LAUNCH_CHECK("k_occ_fill");
+    }
+    // longest tile run list (sizes the slice's LDS stage)
+    std::vector<int32_t> toff(ntiles + 1);
+    SGP_HIP(hipMemcpyAsync(toff.data(), L->tile_off.ptr, sizeof(int32_t) * (ntiles + 1),
+                           hipMemcpyDeviceToHost, st));
+    SGP_HIP(hipStreamSynchronize(st));
+    int mx = 0;
+    for (int64_t t = 0; t < ntiles; ++t) mx = std::max(mx, toff[t + 1] - toff[t]);
+    L->max_tile_runs = mx;
+  }
+  SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost, st));
   SGP_HIP(hipStreamSynchronize(st));
   if (host_word[0] & BF_COLLISION) *retry = true;
+  if (!*retry && (int64_t)host_word[2] != m) {
+    set_error("lattice_build: internal numbering found %u lattice points, expected %lld",
+              host_word[2], (long long)m);
+    return SGP_EHASH;
+  }
   return SGP_OK;
 }
 
@@ -597,12 +1045,9 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
   uint32_t* host_word = nullptr;
   {
     hipError_t e = hipGetDevice(&L->device);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&host_word, 16, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&host_word, sizeof(uint32_t) * (4 + 2 * kMaxD), hipHostMallocDefault);
     if (e != hipSuccess) rc = hip_fail(e, "lattice_build setup", __FILE__, __LINE__);
   }
-  const int D = d + 1;
-  if (rc == SGP_OK) rc = dev_alloc(L->idx, sizeof(int32_t) * n * D);
-  if (rc == SGP_OK) rc = dev_alloc(L->w, sizeof(float) * n * D);
   bool retry = true;
   for (int attempt = 0; rc == SGP_OK && retry && attempt < 4; ++attempt) {
     const unsigned long long seed = 0x5157a11ce5eedull + 0x9e3779b97f4a7c15ull * (unsigned long long)attempt;

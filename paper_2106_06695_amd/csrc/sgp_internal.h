@@ -17,6 +17,16 @@ constexpr int kMaxOrder = 8;    // largest stencil half-width r
 constexpr int kMaxCgCols = 64;  // columns per cg_solve call
 constexpr int kRedBlocks = 512; // blocks (and partial sums) of the reducing vector kernels
 
+// Launch-shape knobs of the MVM kernels. Defaults are the measured best on
+// MI355X; SGP_LDS_BUDGET, SGP_SLICE_ROWS and SGP_SPLAT_STAGE_V in the
+// environment override them (read once per process).
+struct Tuning {
+  int lds_budget;     // bytes of LDS a tile kernel may stage
+  int slice_rows;     // cap on lattice rows per staged slice chunk (0 = budget only; default 128)
+  int splat_stage_v;  // 1: splat stages the tile's values in LDS; 0: reads them from memory
+};
+const Tuning& tuning();
+
 void set_error(const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what, const char* file, int line);
 
@@ -42,6 +52,7 @@ enum KernelKind {
   KK_RESOLVE,
   KK_NEIGHBORS,
   KK_SPLAT,
+  KK_SPLAT_GATHER,
   KK_BLUR,
   KK_SLICE,
   KK_CG_INIT,
@@ -49,6 +60,8 @@ enum KernelKind {
   KK_CG_UPDATE,
   KK_CG_DIR,
   KK_CG_OUT,
+  KK_SORT,
+  KK_ORDER,
   KK_NUM
 };
 
@@ -84,6 +97,12 @@ inline int lanes_for(int C) {
 
 }  // namespace sgp
 
+// One (vertex, weight) or (point, weight) entry of the interpolation matrix W.
+struct sgp_entry {
+  int32_t j;
+  float w;
+};
+
 struct sgp_lattice {
   int64_t n = 0;
   int d = 0;
@@ -96,14 +115,33 @@ struct sgp_lattice {
   double spacing = 0;
   double stencil64[2 * sgp::kMaxOrder + 1] = {};
 
-  sgp::DevBuf idx;   // n x (d+1) int32
-  sgp::DevBuf w;     // n x (d+1) fp32
-  sgp::DevBuf keys;  // m x d int32
-  sgp::DevBuf nbr;   // (d+1) x 2r x m int32: [direction][offset][point]
+  // Internal order: points sorted by their remainder-0 lattice point
+  // (lexicographic), lattice points numbered by first touch in that order.
+  // Sorted points are cut into tiles of tile_points consecutive points (the
+  // entries of tile t are entries t*P*(d+1) onwards, in both orders); each
+  // tile lists the distinct lattice points it touches ("runs"), which the
+  // splat reduces from LDS-staged values and the slice stages into LDS.
+  int tile_points = 256;
+  int64_t ntiles = 0;
+  int64_t nrun = 0;       // total runs over all tiles
+  int max_tile_runs = 0;  // longest tile vertex list
+  sgp::DevBuf perm;       // n uint32: sorted position -> caller's point index
+  sgp::DevBuf loc;        // n(d+1) uint16: run of (sorted point, vertex) within its tile
+  sgp::DevBuf ws;         // n(d+1) fp32: barycentric weight, sorted point order
+  sgp::DevBuf tile_off;   // ntiles+1 int32: first run of each tile
+  sgp::DevBuf tile_verts; // nrun int32: internal lattice point of each run (ascending per tile)
+  sgp::DevBuf run_rel;    // nrun uint16: first entry of each run, relative to its tile's entries
+  sgp::DevBuf ent_lp;     // n(d+1) uint8: point within its tile, entries grouped by run
+  sgp::DevBuf ent_w;      // n(d+1) fp32: weight of each entry, grouped by run
+  sgp::DevBuf occ_ptr;    // m+1 int32: runs of each lattice point in occ
+  sgp::DevBuf occ;        // nrun int32: run indices grouped by lattice point (ascending)
+  sgp::DevBuf nbr;        // (d+1) x 2r x m int32: [direction][offset][internal vertex]
+  sgp::DevBuf int2can;    // m int32: internal vertex -> canonical index
+  sgp::DevBuf keys;       // m x d int32 in canonical order (first occurrence in caller's order)
 
   // work buffers, grown on demand
-  sgp::DevBuf ubuf;   // lattice values, 4 x m x C fp32
-  sgp::DevBuf cgvec;  // CG vectors r, p, q: 3 x n x C fp32
+  sgp::DevBuf ubuf;   // lattice values 4 x m x C, then run partial sums nrun x C
+  sgp::DevBuf cgvec;  // CG vectors x, r, p, q: 4 x n x C fp64
   sgp::DevBuf cgred;  // CG partial sums and per-column scalars
 };
 
@@ -114,6 +152,18 @@ int make_constants(int d, int r, int kernel, const double* ell, double* spacing,
 
 // Launchers used across files.
 int launch_fill_u32(uint32_t* p, size_t count, uint32_t value, hipStream_t s);
+
+// Device-wide exclusive scan (tmp: scan_tmp_words(count) words) and stable
+// LSD radix sort of (key, value) pairs on the low `bits` key bits (tmp:
+// radix_tmp_words(count) words). The sorted pairs end in the *_alt arrays
+// when *result_in_alt is set.
+int scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t count, uint32_t* total,
+                       uint32_t* tmp, hipStream_t s);
+size_t scan_tmp_words(int64_t count);
+size_t radix_tmp_words(int64_t count);
+template <typename K>
+int radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, int64_t count,
+                     int bits, uint32_t* tmp, hipStream_t s, bool* result_in_alt);
 // fp32 values, fp32 lattice accumulation (lattice_mvm)
 int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s);
 // fp64 values and accumulation with the CG epilogue: q = A p, partial sums of p.q

@@ -180,7 +180,9 @@ def test_cg_to_tolerance(sgp, orc):
     x, iters, rel = sgp.cg_solve(lat, _cuda(w.values), w.noise, w.tol, max_iter=500)
     xo, itero, relo, _ = olat.cg(w.values.astype(np.float64), w.noise, w.tol, max_iter=500)
     assert rel[0] <= w.tol
-    assert abs(int(iters[0]) - int(itero[0])) <= 2
+    # near the tolerance the residual curve is flat; rounding-order changes
+    # move the crossing by a few iterations
+    assert abs(int(iters[0]) - int(itero[0])) <= max(2, 0.1 * itero[0])
     xg = x.cpu().numpy().astype(np.float64)
     b = w.values.astype(np.float64)
     res = b - (olat.mvm(xg) + w.noise * xg)
