@@ -116,6 +116,23 @@ int cg_solve(const sgp_lattice* L, const float* rhs, int32_t C, float noise, flo
              int32_t max_iter, float* x, int32_t* iters /* host */,
              float* rel_residual /* host */, void* stream);
 
+/* Gradient of L = sum_{i,c} G[i,c] * (outputscale * K V)[i,c] with respect
+ * to the points X and the log-lengthscales, by one filtering of the 2(d+1)
+ * channels [v, z*v, g, z*g] per column with the kernel derivative
+ * k' = dk/d(dist^2), z = x / l (Section 4.2). For the RBF kernel k' = -k/2,
+ * so K' is -1/2 times this lattice's operator; other kernels give
+ * SGP_EINVAL. The formula assumes a symmetric kernel matrix, so it is the
+ * gradient of the SYMMETRIC-order operator's approximation; with FORWARD or
+ * REVERSE order the same filtering is applied with that order.
+ * X: n x d fp32 device, the points the lattice was built from (same order).
+ * V, G: n x C fp32 device. dX: n x d fp32 device output (or NULL).
+ * dlogell: host array of d doubles (or NULL). Runs in fp64 internally,
+ * allocates stream-ordered work memory of about 16 n (d+1) bytes, and
+ * synchronises `stream`. The dV term of the adjoint is K G itself
+ * (lattice_mvm). */
+int lattice_mvm_grad(const sgp_lattice* L, const float* X, const float* V, const float* G,
+                     int32_t C, float* dX, double* dlogell /* host */, void* stream);
+
 /* Sizes of a built lattice (host outputs, any may be NULL): n, d, the
  * number m of lattice points (m <= n(d+1), Section 5.2) and the device
  * bytes the handle holds. */

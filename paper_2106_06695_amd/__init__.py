@@ -23,8 +23,9 @@ import numpy as np
 from . import _lib
 
 __all__ = [
-    "SGPError", "Lattice", "lattice_build", "lattice_mvm", "cg_solve", "lattice_info",
-    "lattice_export", "lattice_free", "profile", "library_path",
+    "SGPError", "Lattice", "lattice_build", "lattice_mvm", "cg_solve", "lattice_mvm_grad",
+    "lattice_info", "lattice_export", "lattice_free", "lattice_kernel_mvm", "profile",
+    "library_path",
 ]
 
 SYMMETRIC, FORWARD, REVERSE = 0, 1, 2
@@ -162,6 +163,76 @@ def cg_solve(lat: Lattice, rhs, noise: float, tol: float, max_iter: int = 500, x
                                 iters.ctypes.data_as(ctypes.c_void_p),
                                 rel.ctypes.data_as(ctypes.c_void_p), _stream(rhs.device)))
     return x, iters, rel
+
+
+def lattice_mvm_grad(lat: Lattice, X, V, G):
+    """Gradient of sum(G * (outputscale K V)) with respect to X (n x d) and the
+    log-lengthscales (d,), by k' filtering of [v, z v, g, z g] (Section 4.2).
+    Returns (dX tensor, dlogell numpy array)."""
+    import torch
+    px = _dev_f32(X, "X", lat.n)
+    pv = _dev_f32(V, "V", lat.n)
+    pg = _dev_f32(G, "G", lat.n)
+    C = _cols(V)
+    if _cols(G) != C:
+        raise ValueError("V and G must have the same columns")
+    dX = torch.empty_like(X)
+    dl = np.zeros(lat.d, dtype=np.float64)
+    _check(_lib.load().lattice_mvm_grad(lat.handle, px, pv, pg, C, ctypes.c_void_p(dX.data_ptr()),
+                                        dl.ctypes.data_as(ctypes.c_void_p), _stream(X.device)))
+    return dX, dl
+
+
+def _autograd_fn():
+    import torch
+
+    class LatticeKernelMVM(torch.autograd.Function):
+        """out = outputscale * K_lat(X, l) V with the hand-written adjoint:
+        dV = K G (the symmetric operator), dX and dlog l by k' filtering."""
+
+        @staticmethod
+        def forward(ctx, X, log_ell, V, opts):
+            ell = log_ell.detach().double().exp().cpu().numpy()
+            Xc = X.detach().contiguous()
+            Vc = V.detach().contiguous()
+            lat = lattice_build(Xc, ell, **opts)
+            out = lattice_mvm(lat, Vc)
+            ctx.lat = lat
+            ctx.log_ell_meta = (log_ell.dtype, log_ell.device)
+            ctx.save_for_backward(Xc, Vc)
+            return out
+
+        @staticmethod
+        def backward(ctx, G):
+            Xc, Vc = ctx.saved_tensors
+            lat = ctx.lat
+            Gc = G.detach().float().contiguous()
+            dV = lattice_mvm(lat, Gc) if ctx.needs_input_grad[2] else None
+            dX = dlog = None
+            if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+                gX, gl = lattice_mvm_grad(lat, Xc, Vc, Gc)
+                dX = gX if ctx.needs_input_grad[0] else None
+                if ctx.needs_input_grad[1]:
+                    dtype, device = ctx.log_ell_meta
+                    dlog = torch.from_numpy(gl).to(device=device, dtype=dtype)
+            return dX, dlog, dV, None
+
+    return LatticeKernelMVM
+
+
+_FN = None
+
+
+def lattice_kernel_mvm(X, log_lengthscales, V, **opts):
+    """Differentiable lattice MVM for torch autograd (RBF kernel): gradients
+    flow to X, the log-lengthscales and V."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_fn()
+    squeeze = V.dim() == 1
+    Vm = V.unsqueeze(1) if squeeze else V
+    out = _FN.apply(X, log_lengthscales, Vm, opts)
+    return out.squeeze(1) if squeeze else out
 
 
 def lattice_info(lat: Lattice) -> dict:

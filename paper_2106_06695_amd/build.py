@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsimplexgp.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["common.hip", "lattice_build.hip", "lattice_mvm.hip", "cg.hip", "sort.hip"]
+SOURCES = ["common.hip", "lattice_build.hip", "lattice_mvm.hip", "cg.hip", "sort.hip", "grad.hip"]
 ARCH = "gfx950"
 
 

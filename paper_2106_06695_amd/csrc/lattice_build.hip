@@ -1040,6 +1040,7 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
   L->outputscale = o.outputscale;
   double f[kMaxD];
   make_constants(d, o.order, o.kernel, lengthscales, &L->spacing, L->stencil64, f);
+  for (int j = 0; j < d; ++j) L->ell[j] = lengthscales[j];
 
   int rc = SGP_OK;
   uint32_t* host_word = nullptr;

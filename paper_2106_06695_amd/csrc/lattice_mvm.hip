@@ -531,6 +531,10 @@ int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t 
   return mvm_dispatch<double, double>(L, p, nullptr, C, q, s, noise, p, partials);
 }
 
+int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s) {
+  return mvm_dispatch<double, double>(L, V, nullptr, C, out, s, 0.0, nullptr, nullptr);
+}
+
 }  // namespace sgp
 
 using namespace sgp;

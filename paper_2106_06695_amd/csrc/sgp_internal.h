@@ -60,6 +60,7 @@ enum KernelKind {
   KK_CG_UPDATE,
   KK_CG_DIR,
   KK_CG_OUT,
+  KK_GRAD,
   KK_SORT,
   KK_ORDER,
   KK_NUM
@@ -114,6 +115,8 @@ struct sgp_lattice {
   int device = 0;
   double spacing = 0;
   double stencil64[2 * sgp::kMaxOrder + 1] = {};
+  double ell[sgp::kMaxD] = {};  // lengthscales the lattice was built with
+  int64_t solve_rows = 0;       // CG treats points >= solve_rows as absent (0 = none)
 
   // Internal order: points sorted by their remainder-0 lattice point
   // (lexicographic), lattice points numbered by first touch in that order.
@@ -169,4 +172,6 @@ int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_
 // fp64 values and accumulation with the CG epilogue: q = A p, partial sums of p.q
 int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t s, double noise,
            double* partials);
+// fp64 values and accumulation, internal point order, no epilogue
+int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s);
 }  // namespace sgp
