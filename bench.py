@@ -74,6 +74,39 @@ def cpu_baseline(w, n_sample: int, iters: int):
                       f"CG iterations per column (fp64, single thread), {dt:.2f} s"}
 
 
+def serving_bench(workers: int, count: int, rhos=(0.5, 0.9, 1.5), seed: int = 1005):
+    """Served solves (predictive means) at Poisson arrival rates rho / T, with
+    T the mean one-at-a-time service time measured first: p50/p99 latency
+    (completion - arrival) and throughput of the continuous-batching server
+    against the same stream served one request at a time."""
+    import workloads
+    from paper_2106_06695_amd import serve
+
+    warm = workloads.ws5_requests(seed=seed + 1, count=8, mean_gap_s=0.0)
+    serve.Server(workers=workers).run(warm, realtime=False)
+    reqs = workloads.ws5_requests(seed=seed, count=count, mean_gap_s=0.0)
+    solo = serve.Server(workers=1).run(reqs, realtime=False)
+    service = np.array([r.done_s - r.admitted_s for r in solo])
+    T = float(service.mean())
+    iters = np.array([r.iters.max() for r in solo])
+    out = {"requests": count, "workers": workers, "mean_service_ms": T * 1e3,
+           "median_cg_iterations": float(np.median(iters)),
+           "nonconverged": int(sum(int(np.any(r.rel > q.tol)) for r, q in zip(solo, reqs))),
+           "rates": []}
+    for rho in rhos:
+        reqs = workloads.ws5_requests(seed=seed, count=count, mean_gap_s=T / rho)
+        entry = {"rho": rho, "lambda_per_s": rho / T}
+        for name, wk in (("batched", workers), ("one_at_a_time", 1)):
+            srv = serve.Server(workers=wk)
+            res = srv.run(reqs, realtime=True)
+            summ = serve.latency_summary(res)
+            summ["max_reserved_GB"] = srv.max_reserved / 1e9
+            entry[name] = summ
+            print(f"serving rho={rho} {name}: {summ}", file=sys.stderr, flush=True)
+        out["rates"].append(entry)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +116,9 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="points in the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--mvm-reps", type=int, default=20, help="extra timed lattice_mvm calls")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="also run the serving benchmark with this many requests (0 = skip)")
+    ap.add_argument("--serve-workers", type=int, default=8)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -178,6 +214,8 @@ def main(argv=None):
                      "frac_of_hbm_peak": B / mvm_s / 1e9 / HBM_PEAK_GBS},
         "kernels": kernels,
     }
+    if args.serve > 0:
+        line["serving"] = serving_bench(args.serve_workers, args.serve)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n), iters)
     print(json.dumps(line), flush=True)

@@ -72,6 +72,11 @@ typedef struct sgp_opts {
   int32_t blur;      /* enum sgp_blur (default SGP_BLUR_SYMMETRIC) */
   float outputscale; /* sigma_f^2 multiplying the whole operator (default 1) */
   float load_factor; /* hash table fill bound relative to n(d+1), in (0, 0.9] (default 0.5) */
+  int64_t solve_rows; /* cg_solve uses only the first solve_rows points (0 = all, default):
+                         the others splat zero and get x = 0, so a lattice built on
+                         [X; X_test] solves with X's block of the joint operator and one
+                         lattice_mvm of [x; 0] gives the predictive mean at X_test
+                         (Section 2, eq. gp_pred_mean) */
 } sgp_opts;
 
 /* Fill *o with the defaults above (host). */
@@ -84,7 +89,7 @@ void sgp_opts_default(sgp_opts* o);
  * distinct lattice points by first occurrence in the (point, vertex) scan,
  * and tabulates the neighbours of each lattice point along each direction
  * (Section 3.2, Blur).
- * Limits: n >= 1, 1 <= d <= 32, n*(d+1) <= 2^30.
+ * Limits: n >= 1, 1 <= d <= 32, n*(d+1) <= 2^30, 0 <= opts->solve_rows <= n.
  * Errors: SGP_EINVAL (arguments, NaN/Inf in X), SGP_EOVERFLOW (|x_j|/l_j so
  * large that a lattice coordinate leaves int32), SGP_ENOMEM, SGP_EHIP,
  * SGP_EHASH. On success *out receives a handle to free with lattice_free.

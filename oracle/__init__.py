@@ -59,6 +59,7 @@ def _load():
         "orc_slice": (I32, [P, P, I32, P]),
         "orc_blur": (I32, [P, P, I32, I32]),
         "orc_cg": (I32, [P, P, I32, I32, D, D, D, I32, P, P, P, P]),
+        "orc_cg_rows": (I32, [P, P, I32, I32, D, D, D, I32, I64, P, P, P, P]),
         "orc_mvm_grad": (I32, [P, I64, I32, P, I32, I32, I32, P, P, I32, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -190,17 +191,18 @@ class Lattice:
         return U
 
     def cg(self, B, noise: float, tol: float, max_iter: int = 500, mode: int = SYMMETRIC,
-           outputscale: float = 1.0):
+           outputscale: float = 1.0, rows: int = 0):
         """Per-column CG on outputscale*K_lat + noise*I (Section 2, Krylov
-        methods). Returns x, iterations, recursive and true relative residuals."""
+        methods), optionally restricted to the first `rows` points. Returns x,
+        iterations, recursive and true relative residuals."""
         B = self._v(B)
         C = B.shape[1]
         X = np.zeros_like(B)
         iters = np.zeros(C, dtype=np.int32)
         rel = np.zeros(C)
         rel_true = np.zeros(C)
-        _check(_load().orc_cg(self._h, _p(B), C, mode, outputscale, noise, tol, max_iter,
-                              _p(X), _p(iters), _p(rel), _p(rel_true)), "cg")
+        _check(_load().orc_cg_rows(self._h, _p(B), C, mode, outputscale, noise, tol, max_iter,
+                                   int(rows), _p(X), _p(iters), _p(rel), _p(rel_true)), "cg")
         return X, iters, rel, rel_true
 
 

@@ -423,16 +423,23 @@ int orc_blur(const void* lat, double* U, int C, int mode) {
 
 // Conjugate gradients (Hestenes-Stiefel form), one independent recurrence per
 // column of B; a column stops once its recursive residual norm reaches tol
-// relative to ||b|| and is left unchanged afterwards.
-int orc_cg(const void* lat, const double* B, int C, int mode, double os, double noise,
-           double tol, int max_iter, double* X, int32_t* iters, double* rel_rec,
-           double* rel_true) {
+// relative to ||b|| and is left unchanged afterwards. With rows > 0 only the
+// first `rows` points take part: the operator is the lattice operator
+// restricted to them (the other points splat zero and are not solved for).
+int orc_cg_rows(const void* lat, const double* B, int C, int mode, double os, double noise,
+                double tol, int max_iter, int64_t rows, double* X, int32_t* iters,
+                double* rel_rec, double* rel_true) {
   if (!lat || !B || !X || C < 1 || !valid_mode(mode) || max_iter < 1 || !(noise >= 0.0) ||
       !(tol >= 0.0))
     return -1;
   const Lattice& L = *static_cast<const Lattice*>(lat);
-  const int64_t n = L.n;
-  std::vector<double> x(n), r(n), p(n), q(n);
+  const int64_t N = L.n;
+  const int64_t n = (rows > 0 && rows < N) ? rows : N;
+  std::vector<double> x(n), r(n), p(N, 0.0), q(N);
+  auto apply = [&](const std::vector<double>& in, std::vector<double>& out) {
+    mvm(L, in.data(), 1, mode, os, out.data());
+    for (int64_t i = 0; i < n; ++i) out[i] += noise * in[i];
+  };
   for (int c = 0; c < C; ++c) {
     double bb = 0.0;
     for (int64_t i = 0; i < n; ++i) bb += B[i * C + c] * B[i * C + c];
@@ -442,8 +449,7 @@ int orc_cg(const void* lat, const double* B, int C, int mode, double os, double 
     int it = 0;
     double rel = bnorm > 0.0 ? 1.0 : 0.0;
     while (bnorm > 0.0 && it < max_iter) {
-      mvm(L, p.data(), 1, mode, os, q.data());
-      for (int64_t i = 0; i < n; ++i) q[i] += noise * p[i];
+      apply(p, q);
       double pq = 0.0;
       for (int64_t i = 0; i < n; ++i) pq += p[i] * q[i];
       const double alpha = rr / pq;
@@ -458,15 +464,17 @@ int orc_cg(const void* lat, const double* B, int C, int mode, double os, double 
       for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
       rr = rr_new;
     }
-    for (int64_t i = 0; i < n; ++i) X[i * C + c] = x[i];
+    for (int64_t i = 0; i < N; ++i) X[i * C + c] = i < n ? x[i] : 0.0;
     if (iters) iters[c] = it;
     if (rel_rec) rel_rec[c] = rel;
     if (rel_true) {
       if (bnorm > 0.0) {
-        mvm(L, x.data(), 1, mode, os, q.data());
+        std::vector<double> xf(N, 0.0);
+        for (int64_t i = 0; i < n; ++i) xf[i] = x[i];
+        apply(xf, q);
         double res = 0.0;
         for (int64_t i = 0; i < n; ++i) {
-          const double e = B[i * C + c] - (q[i] + noise * x[i]);
+          const double e = B[i * C + c] - q[i];
           res += e * e;
         }
         rel_true[c] = std::sqrt(res) / bnorm;
@@ -476,6 +484,12 @@ int orc_cg(const void* lat, const double* B, int C, int mode, double os, double 
     }
   }
   return 0;
+}
+
+int orc_cg(const void* lat, const double* B, int C, int mode, double os, double noise,
+           double tol, int max_iter, double* X, int32_t* iters, double* rel_rec,
+           double* rel_true) {
+  return orc_cg_rows(lat, B, C, mode, os, noise, tol, max_iter, 0, X, iters, rel_rec, rel_true);
 }
 
 // Gradient of L = sum G .* (K V) with respect to the scaled inputs z = x / l,

@@ -67,6 +67,11 @@ int orc_blur(const void* lat, double* U, int C, int mode);
 int orc_cg(const void* lat, const double* B, int C, int mode, double outputscale,
            double noise, double tol, int max_iter, double* X, int32_t* iters,
            double* rel_rec, double* rel_true);
+/* The same restricted to the first `rows` points (rows <= 0: all): the other
+ * points splat zero, are not solved for, and get x = 0. B and X stay n x C. */
+int orc_cg_rows(const void* lat, const double* B, int C, int mode, double outputscale,
+                double noise, double tol, int max_iter, int64_t rows, double* X,
+                int32_t* iters, double* rel_rec, double* rel_true);
 
 /* Gradient of L = sum_{i,c} G[i,c] * (K_lat V)[i,c] (outputscale 1) with
  * respect to the inputs X (n x d) and the log-lengthscales (d), from one k'

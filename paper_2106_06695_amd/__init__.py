@@ -110,7 +110,7 @@ class Lattice:
 
 def lattice_build(X, lengthscales: Sequence[float], order: int = 1, kernel: str = "rbf",
                   blur: str = "symmetric", outputscale: float = 1.0,
-                  load_factor: float = 0.5) -> Lattice:
+                  load_factor: float = 0.5, solve_rows: int = 0) -> Lattice:
     """Build the lattice of X (n x d fp32 CUDA tensor); see lattice_build in
     include/simplexgp.h (Section 3.2 of the paper: Splat and Blur)."""
     lib = _lib.load()
@@ -128,6 +128,7 @@ def lattice_build(X, lengthscales: Sequence[float], order: int = 1, kernel: str 
     opts.blur = _BLUR[blur]
     opts.outputscale = float(outputscale)
     opts.load_factor = float(load_factor)
+    opts.solve_rows = int(solve_rows)
     h = ctypes.c_void_p()
     _check(lib.lattice_build(px, n, d, ell.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
                              _stream(X.device), ctypes.byref(h)))

@@ -11,7 +11,8 @@ _lib = None
 
 class Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("kernel", ctypes.c_int32), ("blur", ctypes.c_int32),
-                ("outputscale", ctypes.c_float), ("load_factor", ctypes.c_float)]
+                ("outputscale", ctypes.c_float), ("load_factor", ctypes.c_float),
+                ("solve_rows", ctypes.c_int64)]
 
 
 # name -> (restype, argtypes), one entry per declaration in include/simplexgp.h

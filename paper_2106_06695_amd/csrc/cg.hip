@@ -40,7 +40,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
                                                     const uint32_t* __restrict__ perm,
                                                     double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p,
-                                                    int64_t n, int C, double* __restrict__ partials) {
+                                                    int64_t n, int C, int64_t rows,
+                                                    double* __restrict__ partials) {
   constexpr int R = kBlock / G;
   const int lane = threadIdx.x % G;
   const int64_t stride = (int64_t)gridDim.x * R;
@@ -48,7 +49,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
   if (lane < C) {
     for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
       const int64_t e = i * C + lane;
-      const double v = (double)b[(int64_t)perm[i] * C + lane];
+      const int64_t src = perm[i];
+      const double v = (rows > 0 && src >= rows) ? 0.0 : (double)b[src * C + lane];
       x[e] = 0.0;
       r[e] = v;
       p[e] = v;
@@ -195,11 +197,11 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   sgp_lattice* Lm = const_cast<sgp_lattice*>(L);
   const int64_t n = L->n, nC = n * C;
   int rc;
-  if ((rc = dev_reserve(Lm->cgvec, sizeof(double) * 4 * nC))) return rc;
+  if ((rc = dev_reserve(L, Lm->cgvec, sizeof(double) * 4 * nC, s))) return rc;
   // partial sums: kRedBlocks rows from the vector kernels, one row per tile from the slice
   const int64_t nparts = L->ntiles > kRedBlocks ? L->ntiles : kRedBlocks;
   const size_t red_bytes = sizeof(double) * nparts * C + sizeof(CgState) + 256;
-  if ((rc = dev_reserve(Lm->cgred, red_bytes))) return rc;
+  if ((rc = dev_reserve(L, Lm->cgred, red_bytes, s))) return rc;
   double* x64 = (double*)Lm->cgvec.ptr;
   double* r = x64 + nC;
   double* p = r + nC;
@@ -207,18 +209,17 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   double* partials = (double*)Lm->cgred.ptr;
   CgState* st = (CgState*)((char*)Lm->cgred.ptr + ((sizeof(double) * nparts * C + 255) / 256) * 256);
 
-  int32_t* host = nullptr;
-  SGP_HIP(hipHostMalloc((void**)&host, sizeof(int32_t) * 3 * kMaxCgCols, hipHostMallocDefault));
-  struct HostFree {
-    int32_t* p;
-    ~HostFree() { (void)hipHostFree(p); }
-  } host_guard{host};
+  int32_t* host = (int32_t*)pinned_scratch(sizeof(int32_t) * 3 * kMaxCgCols);
+  if (!host) {
+    set_error("cg_solve: pinned host scratch unavailable");
+    return SGP_ENOMEM;
+  }
 
   const dim3 grid(kRedBlocks), block(kBlock);
   {
     ProfScope ps(KK_CG_INIT, s);
     hipLaunchKernelGGL(k_cg_init<G>, grid, block, 0, s, b, (const uint32_t*)L->perm.ptr, x64, r, p, n, C,
-                       partials);
+                       L->solve_rows, partials);
     SGP_LAUNCH_CHECK("k_cg_init");
   }
   {
@@ -270,6 +271,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   SGP_HIP(hipMemcpyAsync(host, st->iters, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
   SGP_HIP(hipMemcpyAsync(host + kMaxCgCols, st->rel, sizeof(float) * C, hipMemcpyDeviceToHost, s));
   SGP_HIP(hipStreamSynchronize(s));
+  mark_use(L, s);
   for (int c = 0; c < C; ++c) {
     if (iters) iters[c] = host[c];
     if (rel) {

@@ -48,35 +48,66 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
   return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
 }
 
-int dev_alloc(DevBuf& b, size_t bytes) {
+int dev_alloc(DevBuf& b, size_t bytes, hipStream_t s) {
   b.ptr = nullptr;
   b.bytes = 0;
   if (bytes == 0) return SGP_OK;
-  hipError_t e = hipMalloc(&b.ptr, bytes);
+  hipError_t e = hipMallocAsync(&b.ptr, bytes, s);
   if (e != hipSuccess) {
     b.ptr = nullptr;
     (void)hipGetLastError();
-    set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    set_error("hipMallocAsync of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
   }
   b.bytes = bytes;
   return SGP_OK;
 }
 
+hipStream_t lib_stream() {
+  constexpr int kMaxDevices = 64;
+  static hipStream_t streams[kMaxDevices] = {};
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!streams[dev]) {
+    // default priority, never blocks on the legacy stream
+    if (hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) streams[dev] = nullptr;
+  }
+  return streams[dev];
+}
+
 void dev_free(DevBuf& b) {
-  if (b.ptr) (void)hipFree(b.ptr);
+  if (b.ptr) (void)hipFreeAsync(b.ptr, lib_stream());
   b.ptr = nullptr;
   b.bytes = 0;
 }
 
-int dev_reserve(DevBuf& b, size_t bytes) {
+void* pinned_scratch(size_t bytes) {
+  constexpr size_t kBytes = 65536;
+  thread_local void* buf = nullptr;
+  if (bytes > kBytes) return nullptr;
+  if (!buf && hipHostMalloc(&buf, kBytes, hipHostMallocDefault) != hipSuccess) buf = nullptr;
+  return buf;
+}
+
+int wait_last_use(const sgp_lattice* L) {
+  if (L && L->last_use) SGP_HIP(hipEventSynchronize(L->last_use));
+  return SGP_OK;
+}
+
+void mark_use(const sgp_lattice* L, hipStream_t s) {
+  if (L && L->last_use) (void)hipEventRecord(L->last_use, s);
+}
+
+int dev_reserve(const sgp_lattice* L, DevBuf& b, size_t bytes, hipStream_t s) {
   if (b.bytes >= bytes) return SGP_OK;
   if (b.ptr) {
-    // the buffer may still be read by queued work on any stream
-    SGP_HIP(hipDeviceSynchronize());
+    int rc = wait_last_use(L);
+    if (rc) return rc;
     dev_free(b);
   }
-  return dev_alloc(b, bytes);
+  return dev_alloc(b, bytes, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,6 +252,7 @@ void sgp_opts_default(sgp_opts* o) {
   o->blur = SGP_BLUR_SYMMETRIC;
   o->outputscale = 1.0f;
   o->load_factor = 0.5f;
+  o->solve_rows = 0;
 }
 
 const char* sgp_last_error(void) { return g_err; }
@@ -247,7 +279,8 @@ int lattice_export(const sgp_lattice* L, int32_t* keys, int32_t* idx, float* w, 
     return SGP_EINVAL;
   }
   SGP_HIP(hipSetDevice(L->device));
-  SGP_HIP(hipDeviceSynchronize());
+  int rc0 = wait_last_use(L);
+  if (rc0) return rc0;
   const int D = L->d + 1, T = 2 * L->order;
   const int64_t n = L->n, m = L->m;
   if (keys) SGP_HIP(hipMemcpy(keys, L->keys.ptr, sizeof(int32_t) * m * L->d, hipMemcpyDeviceToHost));
@@ -295,13 +328,14 @@ int lattice_export(const sgp_lattice* L, int32_t* keys, int32_t* idx, float* w, 
 void lattice_free(sgp_lattice* L) {
   if (!L) return;
   (void)hipSetDevice(L->device);
-  (void)hipDeviceSynchronize();
+  (void)wait_last_use(L);
   for (DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->tile_verts, &L->run_rel,
                    &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->occ, &L->nbr, &L->int2can, &L->keys})
     dev_free(*b);
   dev_free(L->ubuf);
   dev_free(L->cgvec);
   dev_free(L->cgred);
+  if (L->last_use) (void)hipEventDestroy(L->last_use);
   delete L;
 }
 

@@ -197,6 +197,7 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
   std::vector<double> host((size_t)kColBlocks * d);
   SGP_HIP(hipMemcpyAsync(host.data(), part, sizeof(double) * host.size(), hipMemcpyDeviceToHost, s));
   SGP_HIP(hipStreamSynchronize(s));
+  mark_use(L, s);
   if (dlogell) {
     for (int p = 0; p < d; ++p) {
       double acc = 0.0;

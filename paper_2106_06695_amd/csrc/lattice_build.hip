@@ -780,7 +780,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   }
   L->m = m;
   dev_free(L->keys);
-  if ((rc = dev_alloc(L->keys, sizeof(int32_t) * m * d))) return rc;
+  if ((rc = dev_alloc(L->keys, sizeof(int32_t) * m * d, st))) return rc;
   if ((rc = tr.alloc(T_NBRC, sizeof(int32_t) * m * D * T))) return rc;
   int32_t* nbr_can = (int32_t*)tr.ptr[T_NBRC];
   {
@@ -823,11 +823,11 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   for (sgp::DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->tile_verts, &L->run_rel,
                          &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->occ, &L->nbr, &L->int2can})
     dev_free(*b);
-  if ((rc = dev_alloc(L->perm, sizeof(uint32_t) * n))) return rc;
-  if ((rc = dev_alloc(L->loc, sizeof(uint16_t) * Lel))) return rc;
-  if ((rc = dev_alloc(L->ws, sizeof(float) * Lel))) return rc;
-  if ((rc = dev_alloc(L->nbr, sizeof(int32_t) * m * D * T))) return rc;
-  if ((rc = dev_alloc(L->int2can, sizeof(int32_t) * m))) return rc;
+  if ((rc = dev_alloc(L->perm, sizeof(uint32_t) * n, st))) return rc;
+  if ((rc = dev_alloc(L->loc, sizeof(uint16_t) * Lel, st))) return rc;
+  if ((rc = dev_alloc(L->ws, sizeof(float) * Lel, st))) return rc;
+  if ((rc = dev_alloc(L->nbr, sizeof(int32_t) * m * D * T, st))) return rc;
+  if ((rc = dev_alloc(L->int2can, sizeof(int32_t) * m, st))) return rc;
   sgp_entry* pm = (sgp_entry*)tr.ptr[T_PM];
   uint32_t* perm = (uint32_t*)L->perm.ptr;
   {
@@ -918,13 +918,13 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
       return SGP_EHASH;
     }
     L->nrun = Q;
-    if ((rc = dev_alloc(L->tile_off, sizeof(int32_t) * (ntiles + 1)))) return rc;
-    if ((rc = dev_alloc(L->tile_verts, sizeof(int32_t) * Q))) return rc;
-    if ((rc = dev_alloc(L->run_rel, sizeof(uint16_t) * Q))) return rc;
-    if ((rc = dev_alloc(L->ent_lp, sizeof(uint8_t) * Lel))) return rc;
-    if ((rc = dev_alloc(L->ent_w, sizeof(float) * Lel))) return rc;
-    if ((rc = dev_alloc(L->occ_ptr, sizeof(int32_t) * (m + 1)))) return rc;
-    if ((rc = dev_alloc(L->occ, sizeof(int32_t) * Q))) return rc;
+    if ((rc = dev_alloc(L->tile_off, sizeof(int32_t) * (ntiles + 1), st))) return rc;
+    if ((rc = dev_alloc(L->tile_verts, sizeof(int32_t) * Q, st))) return rc;
+    if ((rc = dev_alloc(L->run_rel, sizeof(uint16_t) * Q, st))) return rc;
+    if ((rc = dev_alloc(L->ent_lp, sizeof(uint8_t) * Lel, st))) return rc;
+    if ((rc = dev_alloc(L->ent_w, sizeof(float) * Lel, st))) return rc;
+    if ((rc = dev_alloc(L->occ_ptr, sizeof(int32_t) * (m + 1), st))) return rc;
+    if ((rc = dev_alloc(L->occ, sizeof(int32_t) * Q, st))) return rc;
     {
       ProfScope ps(KK_ORDER, st);
       hipLaunchKernelGGL(k_run_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, sv,
@@ -1025,6 +1025,10 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
     set_error("lattice_build: outputscale must be finite");
     return SGP_EINVAL;
   }
+  if (o.solve_rows < 0 || o.solve_rows > n) {
+    set_error("lattice_build: solve_rows must be in [0, n]");
+    return SGP_EINVAL;
+  }
   if (!(o.load_factor > 0.0f && o.load_factor <= 0.9f)) {
     set_error("lattice_build: load_factor must be in (0, 0.9]");
     return SGP_EINVAL;
@@ -1038,16 +1042,21 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
   L->kernel = o.kernel;
   L->blur = o.blur;
   L->outputscale = o.outputscale;
+  L->solve_rows = o.solve_rows;
   double f[kMaxD];
   make_constants(d, o.order, o.kernel, lengthscales, &L->spacing, L->stencil64, f);
   for (int j = 0; j < d; ++j) L->ell[j] = lengthscales[j];
 
   int rc = SGP_OK;
-  uint32_t* host_word = nullptr;
+  uint32_t* host_word = (uint32_t*)pinned_scratch(sizeof(uint32_t) * (4 + 2 * kMaxD));
   {
     hipError_t e = hipGetDevice(&L->device);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&host_word, sizeof(uint32_t) * (4 + 2 * kMaxD), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&L->last_use, hipEventDisableTiming);
     if (e != hipSuccess) rc = hip_fail(e, "lattice_build setup", __FILE__, __LINE__);
+    if (!host_word && rc == SGP_OK) {
+      set_error("lattice_build: pinned host scratch unavailable");
+      rc = SGP_ENOMEM;
+    }
   }
   bool retry = true;
   for (int attempt = 0; rc == SGP_OK && retry && attempt < 4; ++attempt) {
@@ -1061,8 +1070,8 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
   if (rc == SGP_OK) {
     hipError_t e = hipStreamSynchronize(st);  // transient buffers are released on the stream
     if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
+    mark_use(L, st);
   }
-  if (host_word) (void)hipHostFree(host_word);
   if (rc != SGP_OK) {
     lattice_free(L);
     return rc;

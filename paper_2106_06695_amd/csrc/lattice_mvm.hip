@@ -274,7 +274,9 @@ __global__ __launch_bounds__(kBlock) void k_slice_tile(const int32_t* __restrict
                                                        const uint32_t* __restrict__ perm, int64_t n,
                                                        int P, int D, int C, int RC, TU scale, TV noise,
                                                        const TV* __restrict__ p,
-                                                       double* __restrict__ partials) {
+                                                       double* __restrict__ partials,
+                                                       const uint32_t* __restrict__ mperm,
+                                                       int64_t mrows) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int R = kBlock / G;
   const int lane = threadIdx.x % G, row = threadIdx.x / G;
@@ -354,6 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_slice_tile(const int32_t* __restrict
       if (CG) {
         const TV pv = p[pt * C + c];
         o = fma_t(noise, pv, o);
+        if (mrows > 0 && (int64_t)mperm[pt] >= mrows) o = 0;  // not solved for
         dot += (double)pv * (double)o;
       }
       out[(perm ? (int64_t)perm[pt] : pt) * C + c] = o;
@@ -462,12 +465,14 @@ int mvm_g(const sgp_lattice* L, const TV* V, const uint32_t* perm, int C, TV* ou
     hipLaunchKernelGGL((k_slice_tile<TV, TU, G, true>), tgrid, dim3(kBlock), lds, s,
                        (const int32_t*)L->tile_off.ptr, (const int32_t*)L->tile_verts.ptr,
                        (const uint16_t*)L->loc.ptr, (const float*)L->ws.ptr, cur[0], out, perm,
-                       L->n, P, D, C, RC, scale, noise, p, partials);
+                       L->n, P, D, C, RC, scale, noise, p, partials, (const uint32_t*)L->perm.ptr,
+                       L->solve_rows);
   } else {
     hipLaunchKernelGGL((k_slice_tile<TV, TU, G, false>), tgrid, dim3(kBlock), lds, s,
                        (const int32_t*)L->tile_off.ptr, (const int32_t*)L->tile_verts.ptr,
                        (const uint16_t*)L->loc.ptr, (const float*)L->ws.ptr, cur[0], out, perm,
-                       L->n, P, D, C, RC, scale, (TV)0, (const TV*)nullptr, nullptr);
+                       L->n, P, D, C, RC, scale, (TV)0, (const TV*)nullptr, nullptr,
+                       (const uint32_t*)nullptr, (int64_t)0);
   }
   SGP_LAUNCH_CHECK("k_slice_tile");
   return SGP_OK;
@@ -505,8 +510,8 @@ int chunk_lanes(const sgp_lattice* L, int C, size_t elem) {
 template <typename TV, typename TU>
 int mvm_dispatch(const sgp_lattice* L, const TV* V, const uint32_t* perm, int C, TV* out,
                  hipStream_t s, TV noise, const TV* p, double* partials) {
-  int rc = dev_reserve(const_cast<sgp_lattice*>(L)->ubuf,
-                       sizeof(TU) * (4 * L->m + L->nrun) * (size_t)C);
+  int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf,
+                       sizeof(TU) * (4 * L->m + L->nrun) * (size_t)C, s);
   if (rc) return rc;
   switch (chunk_lanes(L, C, sizeof(TU))) {
     case 1: return mvm_g<TV, TU, 1>(L, V, perm, C, out, s, noise, p, partials);
@@ -556,5 +561,7 @@ extern "C" int lattice_mvm(const sgp_lattice* L, const float* values, int32_t C,
     set_error("lattice_mvm: out overlaps values");
     return SGP_EINVAL;
   }
-  return mvm_into(L, values, C, out, (hipStream_t)stream);
+  const int rc = mvm_into(L, values, C, out, (hipStream_t)stream);
+  if (rc == SGP_OK) mark_use(L, (hipStream_t)stream);
+  return rc;
 }

@@ -83,10 +83,16 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-int dev_alloc(DevBuf& b, size_t bytes);
+// Device memory is stream-ordered: allocated on the stream of the call that
+// first needs it, released on a library-owned stream once the lattice's last
+// use (an event recorded at the end of every call) has completed. Nothing in
+// the library synchronises the whole device, so lattices driven from
+// different streams overlap.
+int dev_alloc(DevBuf& b, size_t bytes, hipStream_t s);
 void dev_free(DevBuf& b);
-// Grow (never shrink) a work buffer; contents are not preserved.
-int dev_reserve(DevBuf& b, size_t bytes);
+hipStream_t lib_stream();
+// Pinned host scratch of at least `bytes` (<= 64 KiB), one per host thread.
+void* pinned_scratch(size_t bytes);
 
 // Lanes that share one row of C channels: the smallest power of two >= C,
 // capped at one wavefront.
@@ -116,7 +122,7 @@ struct sgp_lattice {
   double spacing = 0;
   double stencil64[2 * sgp::kMaxOrder + 1] = {};
   double ell[sgp::kMaxD] = {};  // lengthscales the lattice was built with
-  int64_t solve_rows = 0;       // CG treats points >= solve_rows as absent (0 = none)
+  int64_t solve_rows = 0;       // CG solves on the first solve_rows points only (0 = all)
 
   // Internal order: points sorted by their remainder-0 lattice point
   // (lexicographic), lattice points numbered by first touch in that order.
@@ -142,6 +148,8 @@ struct sgp_lattice {
   sgp::DevBuf int2can;    // m int32: internal vertex -> canonical index
   sgp::DevBuf keys;       // m x d int32 in canonical order (first occurrence in caller's order)
 
+  hipEvent_t last_use = nullptr;  // recorded at the end of every call on the lattice
+
   // work buffers, grown on demand
   sgp::DevBuf ubuf;   // lattice values 4 x m x C, then run partial sums nrun x C
   sgp::DevBuf cgvec;  // CG vectors x, r, p, q: 4 x n x C fp64
@@ -149,6 +157,14 @@ struct sgp_lattice {
 };
 
 namespace sgp {
+// Grow (never shrink) a work buffer of L; contents are not preserved. Waits
+// for L's last use before releasing a smaller buffer.
+int dev_reserve(const sgp_lattice* L, DevBuf& b, size_t bytes, hipStream_t s);
+// Record the end of a call on L (its last use) on stream s.
+void mark_use(const sgp_lattice* L, hipStream_t s);
+// Wait for L's last recorded use.
+int wait_last_use(const sgp_lattice* L);
+
 // Host-side constants (Section 4.1 and Section 3.2 Splat).
 int make_constants(int d, int r, int kernel, const double* ell, double* spacing,
                    double* stencil, double* f);

@@ -500,3 +500,24 @@ def test_lattice_gradient_tracks_exact_gradient(orc):
     gz = _dense_grad_z(Z / np.sqrt(s2), V, G) / np.sqrt(s2)
     cos = (dX.ravel() @ gz.ravel()) / np.linalg.norm(dX) / np.linalg.norm(gz)
     assert cos > 0.95, cos  # measured 0.981 at n = 2000, d = 3
+
+
+def test_cg_restricted_rows_is_the_submatrix_solve(orc):
+    """CG on the first n_train points of a lattice built on [X; X*] solves
+    with the submatrix of the joint operator (reading for the predictive
+    mean, Section 2 eq. gp_pred_mean)."""
+    w = workloads.small_case(13, 500, 3, channels=1, kind="mixture")
+    n_train = 380
+    lat = orc.Lattice(w.X, w.lengthscales)
+    K = lat.mvm(np.eye(w.n))
+    A = K[:n_train, :n_train] + 0.1 * np.eye(n_train)
+    b = np.zeros((w.n, 1))
+    b[:n_train] = w.values[:n_train]
+    x, iters, rel, rel_true = lat.cg(b, 0.1, 1e-11, max_iter=3000, rows=n_train)
+    np.testing.assert_allclose(x[:n_train, 0], np.linalg.solve(A, b[:n_train, 0]), rtol=0,
+                               atol=1e-8 * np.abs(x).max())
+    assert np.all(x[n_train:] == 0.0)
+    # predictive mean: one MVM of [alpha; 0], test rows
+    mu = lat.mvm(np.concatenate([x[:n_train], np.zeros((w.n - n_train, 1))]))[n_train:, 0]
+    np.testing.assert_allclose(mu, K[n_train:, :n_train] @ x[:n_train, 0], rtol=1e-10,
+                               atol=1e-12)
