@@ -88,6 +88,8 @@ def serving_bench(workers: int, count: int, rhos=(0.5, 0.9, 1.5), seed: int = 10
     solo = serve.Server(workers=1).run(reqs, realtime=False)
     service = np.array([r.done_s - r.admitted_s for r in solo])
     T = float(service.mean())
+    print(f"serving: one-at-a-time service {T * 1e3:.2f} ms mean over {count} requests",
+          file=sys.stderr, flush=True)
     iters = np.array([r.iters.max() for r in solo])
     out = {"requests": count, "workers": workers, "mean_service_ms": T * 1e3,
            "median_cg_iterations": float(np.median(iters)),
@@ -185,6 +187,20 @@ def main(argv=None):
     torch.cuda.synchronize()
     mvm_s = (time.perf_counter() - t0) / args.mvm_reps
     B = mvm_bytes(n, d, lat.m, C, 1, sym)
+
+    # the same 20 iterations as C separate single-column solves
+    sep_x = torch.empty((n, 1), dtype=torch.float32, device=V.device)
+    cols = [V[:, c:c + 1].contiguous() for c in range(C)]
+    sgp.cg_solve(lat, cols[0], w.noise, 0.0, max_iter=iters, x=sep_x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sgp.cg_solve(lat, V, w.noise, 0.0, max_iter=iters, x=x)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for c in range(C):
+        sgp.cg_solve(lat, cols[c], w.noise, 0.0, max_iter=iters, x=sep_x)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
     lat.free()
 
     line = {
@@ -212,6 +228,9 @@ def main(argv=None):
         "mvm_only": {"ms": mvm_s * 1e3, "points_ch_per_s": n * C / mvm_s,
                      "algo_bytes": B, "algo_GBps": B / mvm_s / 1e9,
                      "frac_of_hbm_peak": B / mvm_s / 1e9 / HBM_PEAK_GBS},
+        "batched_vs_separate": {"cg_iterations": iters, "batched_C16_ms": (t1 - t0) * 1e3,
+                                "separate_16x_C1_ms": (t2 - t1) * 1e3,
+                                "speedup": (t2 - t1) / (t1 - t0)},
         "kernels": kernels,
     }
     if args.serve > 0:

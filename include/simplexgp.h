@@ -161,6 +161,15 @@ void lattice_free(sgp_lattice* L);
 /* Message of the last failure on this thread ("" if none). */
 const char* sgp_last_error(void);
 
+/* CG iterations as HIP graphs (process-wide switch, default on). When on,
+ * cg_solve records a block of iterations (4 between convergence polls, 8
+ * when tol == 0) into a graph once per call and replays it, which removes
+ * the per-launch host cost; the arithmetic and results are identical to the
+ * launch-by-launch path, which runs when the switch is off, while the
+ * profiler is enabled, and for the iterations that do not fill a block.
+ * Returns the previous setting. */
+int sgp_cg_graph_enable(int on);
+
 /* Kernel timing with HIP events, for benchmarks. While enabled, every
  * kernel launch of the library is bracketed by two events on its stream.
  * sgp_profile_read synchronises the recorded events and reports, for one

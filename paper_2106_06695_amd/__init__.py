@@ -259,6 +259,12 @@ def lattice_free(lat: Lattice):
     lat.free()
 
 
+def cg_graph_enable(on: bool) -> bool:
+    """Turn graph replay of CG iterations on or off (process-wide); returns
+    the previous setting. Results do not depend on it."""
+    return bool(_lib.load().sgp_cg_graph_enable(1 if on else 0))
+
+
 class profile:
     """Context manager: per-kernel HIP-event timings of library launches.
 

@@ -27,6 +27,7 @@ SIGNATURES = {
     "lattice_export": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "lattice_free": (None, [_P]),
     "sgp_last_error": (ctypes.c_char_p, []),
+    "sgp_cg_graph_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_profile_reset": (ctypes.c_int, []),
     "sgp_profile_kinds": (ctypes.c_int, []),

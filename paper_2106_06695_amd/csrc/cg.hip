@@ -228,40 +228,99 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
                        (int)SM_START, (double)tol);
     SGP_LAUNCH_CHECK("k_cg_scalar");
   }
-  // polling interval: each poll drains the queue, so poll less when the
-  // caller asked for a fixed iteration count
-  const int poll = tol > 0.f ? 4 : max_iter;
-  for (int it = 0; it < max_iter; ++it) {
-    if ((rc = mvm_cg(L, p, C, q, s, (double)noise, partials))) return rc;
+  // One iteration: q = A p (with the p.q partials from the slice), alpha,
+  // x and r, convergence and beta, p. Nothing here talks to the host, so a
+  // block of iterations can be recorded as a graph.
+  auto iterate = [&](hipStream_t st_) -> int {
+    int rc_ = mvm_cg(L, p, C, q, st_, (double)noise, partials);
+    if (rc_) return rc_;
     {
-      ProfScope ps(KK_CG_SCALAR, s);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, partials, L->ntiles, C, st,
+      ProfScope ps(KK_CG_SCALAR, st_);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, partials, L->ntiles, C, st,
                          (int)SM_ALPHA, (double)tol);
       SGP_LAUNCH_CHECK("k_cg_scalar");
     }
     {
-      ProfScope ps(KK_CG_UPDATE, s);
-      hipLaunchKernelGGL(k_cg_update<G>, grid, block, 0, s, x64, r, p, q, n, C, st, partials);
+      ProfScope ps(KK_CG_UPDATE, st_);
+      hipLaunchKernelGGL(k_cg_update<G>, grid, block, 0, st_, x64, r, p, q, n, C, st, partials);
       SGP_LAUNCH_CHECK("k_cg_update");
     }
     {
-      ProfScope ps(KK_CG_SCALAR, s);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, partials, (int64_t)kRedBlocks, C, st,
-                         (int)SM_BETA, (double)tol);
+      ProfScope ps(KK_CG_SCALAR, st_);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, partials, (int64_t)kRedBlocks, C,
+                         st, (int)SM_BETA, (double)tol);
       SGP_LAUNCH_CHECK("k_cg_scalar");
     }
     {
-      ProfScope ps(KK_CG_DIR, s);
-      hipLaunchKernelGGL(k_cg_dir<G>, grid, block, 0, s, r, p, n, C, st);
+      ProfScope ps(KK_CG_DIR, st_);
+      hipLaunchKernelGGL(k_cg_dir<G>, grid, block, 0, st_, r, p, n, C, st);
       SGP_LAUNCH_CHECK("k_cg_dir");
     }
-    if ((it + 1) % poll == 0 && it + 1 < max_iter) {
-      SGP_HIP(hipMemcpyAsync(host, st->active, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
-      SGP_HIP(hipStreamSynchronize(s));
-      bool any = false;
-      for (int c = 0; c < C; ++c) any |= host[c] != 0;
-      if (!any) break;
+    return SGP_OK;
+  };
+  // Polls read the per-column active flags; each one drains the queue, so
+  // none are made when the caller asked for a fixed iteration count.
+  auto all_done = [&](bool* done) -> int {
+    SGP_HIP(hipMemcpyAsync(host, st->active, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+    SGP_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    for (int c = 0; c < C; ++c) any |= host[c] != 0;
+    *done = !any;
+    return SGP_OK;
+  };
+  const bool polling = tol > 0.f;
+  const int blk = polling ? 4 : 8;
+  // The first block and one more iteration run launch by launch: the first
+  // MVM sizes the lattice's work buffers (a graph must not allocate), and a
+  // solve that converges within them never pays for recording a graph.
+  int it = 0;
+  bool done = false;
+  const int eager_head = blk + 1 < max_iter ? blk + 1 : max_iter;
+  for (; it < eager_head && !done; ++it) {
+    if ((rc = iterate(s))) return rc;
+    if (polling && (it + 1) % blk == 0 && it + 1 < max_iter)
+      if ((rc = all_done(&done))) return rc;
+  }
+  if (!done && polling && it < max_iter && it % blk != 0)
+    if ((rc = all_done(&done))) return rc;
+  if (!done && max_iter - it >= 2 * blk && cg_graphs_enabled() && !profiling()) {
+    hipStream_t cs = capture_stream();
+    if (!cs) {
+      set_error("cg_solve: could not create a capture stream");
+      return SGP_EHIP;
     }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct GraphGuard {
+      hipGraph_t* g;
+      hipGraphExec_t* e;
+      hipStream_t s;
+      ~GraphGuard() {
+        if (*e) {
+          (void)hipStreamSynchronize(s);
+          (void)hipGraphExecDestroy(*e);
+        }
+        if (*g) (void)hipGraphDestroy(*g);
+      }
+    } guard{&graph, &exec, s};
+    SGP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int crc = SGP_OK;
+    for (int b = 0; b < blk && !crc; ++b) crc = iterate(cs);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (crc) return crc;
+    SGP_HIP(ce);
+    SGP_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    while (!done && max_iter - it >= blk) {
+      SGP_HIP(hipGraphLaunch(exec, s));
+      it += blk;
+      if (polling && it < max_iter)
+        if ((rc = all_done(&done))) return rc;
+    }
+  }
+  for (; it < max_iter && !done; ++it) {
+    if ((rc = iterate(s))) return rc;
+    if (polling && (it + 1) % blk == 0 && it + 1 < max_iter)
+      if ((rc = all_done(&done))) return rc;
   }
   {
     ProfScope ps(KK_CG_OUT, s);

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -26,11 +27,14 @@ int env_int(const char* name, int dflt) {
 const Tuning& tuning() {
   static const Tuning t = [] {
     Tuning k;
-    k.lds_budget = env_int("SGP_LDS_BUDGET", 65536);
-    if (k.lds_budget < 8192) k.lds_budget = 8192;
-    if (k.lds_budget > 65536) k.lds_budget = 65536;
-    k.slice_rows = env_int("SGP_SLICE_ROWS", 128);
-    k.splat_stage_v = env_int("SGP_SPLAT_STAGE_V", 1);
+    k.lds_budget = env_int("SGP_LDS_BUDGET", 131072);
+    if (k.lds_budget < 16384) k.lds_budget = 16384;
+    if (k.lds_budget > 163840) k.lds_budget = 163840;
+    k.slice_lds_budget = env_int("SGP_SLICE_LDS_BUDGET", 131072);
+    if (k.slice_lds_budget < 16384) k.slice_lds_budget = 16384;
+    if (k.slice_lds_budget > 163840) k.slice_lds_budget = 163840;
+    k.blocks_per_cu = env_int("SGP_TILE_BLOCKS_PER_CU", 0);
+    if (k.blocks_per_cu < 0) k.blocks_per_cu = 0;
     return k;
   }();
   return t;
@@ -243,6 +247,26 @@ int launch_fill_u32(uint32_t* p, size_t count, uint32_t value, hipStream_t s) {
 
 using namespace sgp;
 
+namespace sgp {
+namespace {
+std::atomic<int> g_cg_graph{1};
+}
+bool profiling() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+bool cg_graphs_enabled() { return g_cg_graph.load() != 0; }
+hipStream_t capture_stream() {
+  constexpr int kMaxDevices = 64;
+  thread_local hipStream_t streams[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+}  // namespace sgp
+
 extern "C" {
 
 void sgp_opts_default(sgp_opts* o) {
@@ -268,7 +292,7 @@ int lattice_info(const sgp_lattice* L, int64_t* n, int32_t* d, int64_t* m, int64
   if (device_bytes)
     *device_bytes = (int64_t)(L->perm.bytes + L->loc.bytes + L->ws.bytes + L->tile_off.bytes +
                               L->tile_verts.bytes + L->run_rel.bytes + L->ent_lp.bytes + L->ent_w.bytes +
-                              L->occ_ptr.bytes + L->occ.bytes + L->nbr.bytes + L->int2can.bytes +
+                              L->occ_ptr.bytes + L->run_dst.bytes + L->nbr.bytes + L->int2can.bytes +
                               L->keys.bytes + L->ubuf.bytes + L->cgvec.bytes + L->cgred.bytes);
   return SGP_OK;
 }
@@ -330,7 +354,7 @@ void lattice_free(sgp_lattice* L) {
   (void)hipSetDevice(L->device);
   (void)wait_last_use(L);
   for (DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->tile_verts, &L->run_rel,
-                   &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->occ, &L->nbr, &L->int2can, &L->keys})
+                   &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->run_dst, &L->nbr, &L->int2can, &L->keys})
     dev_free(*b);
   dev_free(L->ubuf);
   dev_free(L->cgvec);
@@ -338,6 +362,9 @@ void lattice_free(sgp_lattice* L) {
   if (L->last_use) (void)hipEventDestroy(L->last_use);
   delete L;
 }
+
+
+int sgp_cg_graph_enable(int on) { return g_cg_graph.exchange(on != 0 ? 1 : 0); }
 
 int sgp_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

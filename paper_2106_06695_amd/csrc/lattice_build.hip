@@ -603,15 +603,16 @@ __global__ __launch_bounds__(kBlock) void k_occ_keys(const int32_t* __restrict__
   }
 }
 
-// Runs sorted by lattice point: start of each point's list.
+// Runs sorted (stably) by lattice point: row o of the splat's partial buffer
+// belongs to run val[o]; each lattice point's rows are contiguous.
 __global__ __launch_bounds__(kBlock) void k_occ_fill(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ val, int64_t Q,
                                                      int64_t m, int32_t* __restrict__ occ_ptr,
-                                                     int32_t* __restrict__ occ) {
+                                                     int32_t* __restrict__ run_dst) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < Q; o += stride) {
     const uint32_t j = key[o];
-    occ[o] = (int32_t)val[o];
+    run_dst[val[o]] = (int32_t)o;
     if (o == 0 || key[o - 1] != j) occ_ptr[j] = (int32_t)o;
     if (o == Q - 1) occ_ptr[m] = (int32_t)Q;
   }
@@ -821,10 +822,11 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   uint32_t* vb = (uint32_t*)tr.ptr[T_VB];
   uint32_t* sort_tmp = (uint32_t*)tr.ptr[T_SORTTMP];
   for (sgp::DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->tile_verts, &L->run_rel,
-                         &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->occ, &L->nbr, &L->int2can})
+                         &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->run_dst, &L->nbr, &L->int2can})
     dev_free(*b);
   if ((rc = dev_alloc(L->perm, sizeof(uint32_t) * n, st))) return rc;
-  if ((rc = dev_alloc(L->loc, sizeof(uint16_t) * Lel, st))) return rc;
+  // two spare slots: the slice reads slots in aligned pairs
+  if ((rc = dev_alloc(L->loc, sizeof(uint16_t) * (Lel + 2), st))) return rc;
   if ((rc = dev_alloc(L->ws, sizeof(float) * Lel, st))) return rc;
   if ((rc = dev_alloc(L->nbr, sizeof(int32_t) * m * D * T, st))) return rc;
   if ((rc = dev_alloc(L->int2can, sizeof(int32_t) * m, st))) return rc;
@@ -881,8 +883,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   // ---- tiles of consecutive sorted points, their runs, and runs per lattice point
   {
     // tile size: at most 256 points (a point index fits 8 bits) and 4096
-    // entries (the tile kernels stage a tile's entries in LDS)
-    const int P = std::min(256, 4096 / D);
+    // entries (the tile kernels stage a tile's entries in LDS); a multiple
+    // of 4, so that every tile's entries start 4-byte aligned in the 8- and
+    // 16-bit arrays
+    const int P = std::min(256, 4096 / D) & ~3;
     L->tile_points = P;
     const int64_t ntiles = (n + P - 1) / P;
     L->ntiles = ntiles;
@@ -921,10 +925,11 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     if ((rc = dev_alloc(L->tile_off, sizeof(int32_t) * (ntiles + 1), st))) return rc;
     if ((rc = dev_alloc(L->tile_verts, sizeof(int32_t) * Q, st))) return rc;
     if ((rc = dev_alloc(L->run_rel, sizeof(uint16_t) * Q, st))) return rc;
-    if ((rc = dev_alloc(L->ent_lp, sizeof(uint8_t) * Lel, st))) return rc;
+    // four spare bytes: the splat reads entry points four at a time
+    if ((rc = dev_alloc(L->ent_lp, sizeof(uint8_t) * (Lel + 4), st))) return rc;
     if ((rc = dev_alloc(L->ent_w, sizeof(float) * Lel, st))) return rc;
     if ((rc = dev_alloc(L->occ_ptr, sizeof(int32_t) * (m + 1), st))) return rc;
-    if ((rc = dev_alloc(L->occ, sizeof(int32_t) * Q, st))) return rc;
+    if ((rc = dev_alloc(L->run_dst, sizeof(int32_t) * Q, st))) return rc;
     {
       ProfScope ps(KK_ORDER, st);
       hipLaunchKernelGGL(k_run_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, sv,
@@ -952,7 +957,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
       ProfScope ps(KK_ORDER, st);
       hipLaunchKernelGGL(k_occ_fill, dim3(grid_for(Q, kBlock, 16384)), dim3(kBlock), 0, st,
                          occ_alt ? k32b : k32a, occ_alt ? vb : va, Q, m, (int32_t*)L->occ_ptr.ptr,
-                         (int32_t*)L->occ.ptr);
+                         (int32_t*)L->run_dst.ptr);
       SGP_LAUNCH_CHECK("k_occ_fill");
     }
     // longest tile run list (sizes the slice's LDS stage)

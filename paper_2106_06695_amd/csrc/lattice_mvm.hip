@@ -47,132 +47,335 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// LDS layout of k_splat_tile: values [P][G] (TU) | weights [P*D] (fp32) |
-// run starts [runs+1] (uint16) | entry points [P*D] (uint8).
-template <typename TU>
-__host__ __device__ inline size_t splat_lds_bytes(int P, int D, int runs, int G, bool stage_v) {
-  size_t b = stage_v ? sizeof(TU) * (size_t)P * G : 0;
-  b += sizeof(float) * (size_t)P * D;
-  b += sizeof(uint16_t) * (size_t)(runs + 1);
-  b = (b + 3) & ~(size_t)3;
-  b += (size_t)P * D;
-  return (b + 15) & ~(size_t)15;
+// 16-byte vectors for LDS and global accesses of lattice and point rows.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  typedef dvec2 T;
+  static constexpr int N = 2;
+};
+template <>
+struct Vec16<float> {
+  typedef fvec4 T;
+  static constexpr int N = 4;
+};
+
+// Read (or write) W consecutive elements at p, as 16-byte vectors when W
+// elements span whole vectors (p is then 16-byte aligned by construction).
+template <typename T, int W>
+__device__ __forceinline__ void read_row(const T* p, T (&o)[W]) {
+  constexpr int N = Vec16<T>::N;
+  if constexpr (W % N == 0) {
+#pragma unroll
+    for (int i = 0; i < W / N; ++i) {
+      const typename Vec16<T>::T x = *(const typename Vec16<T>::T*)(p + i * N);
+#pragma unroll
+      for (int j = 0; j < N; ++j) o[i * N + j] = x[j];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; ++i) o[i] = p[i];
+  }
+}
+template <typename T, int W>
+__device__ __forceinline__ void write_row(T* p, const T (&v)[W]) {
+  constexpr int N = Vec16<T>::N;
+  if constexpr (W % N == 0) {
+#pragma unroll
+    for (int i = 0; i < W / N; ++i) {
+      typename Vec16<T>::T x;
+#pragma unroll
+      for (int j = 0; j < N; ++j) x[j] = v[i * N + j];
+      *(typename Vec16<T>::T*)(p + i * N) = x;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; ++i) p[i] = v[i];
+  }
 }
 
-// Copy a tile's n (<= kMaxTileEntries) entries (weight + small index) to
-// LDS with every load of the thread issued before its stores.
+// Persistent tile kernels: block b runs on XCD b % 8 and takes work items
+// from a contiguous range owned by its XCD, striding over it with the other
+// blocks of that XCD.
+__device__ __forceinline__ void xcd_items(int64_t items, int64_t* first, int64_t* end, int64_t* step) {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t x = b % kXcds, k = b / kXcds;
+  const int64_t per = nb / kXcds, rem = nb % kXcds;
+  const int64_t before = x * per + (x < rem ? x : rem);
+  const int64_t mine = per + (x < rem ? 1 : 0);
+  const int64_t lo = items * before / nb;
+  const int64_t hi = items * (before + mine) / nb;
+  *first = lo + k;
+  *end = hi;
+  *step = mine;
+}
+
+// Per-thread register shapes of the tile kernels (NT threads per block, at
+// most 256 points and kMaxTileEntries entries and runs per tile).
 constexpr int kMaxTileEntries = 4096;
-template <typename IDX>
-__device__ __forceinline__ void stage_entries(const float* __restrict__ w, const IDX* __restrict__ ix,
-                                              int n, float* lw, IDX* lix) {
-  constexpr int kPer = kMaxTileEntries / kBlock;
-  float wt[kPer];
-  IDX it[kPer];
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int i = threadIdx.x + u * kBlock;
-    if (i < n) {
-      wt[u] = w[i];
-      it[u] = ix[i];
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int i = threadIdx.x + u * kBlock;
-    if (i < n) {
-      lw[i] = wt[u];
-      lix[i] = it[u];
-    }
-  }
+constexpr int kSplatBlock = 512;   // two blocks per CU
+constexpr int kSliceBlock = 1024;  // one block per CU
+template <typename TU, int G, int NT>
+struct TileShape {
+  static constexpr int kPts = 256;
+  static constexpr int EPT = kMaxTileEntries / NT;  // entries per thread
+  static constexpr int RPT = 2;                      // runs prefetched per thread (splat)
+  static constexpr int VPT = (kPts * G) / NT > 0 ? (kPts * G) / NT : 1;  // point values
+  static constexpr int VW = G < 4 ? G : 4;  // channels per lane
+  static constexpr int LPR = G / VW;        // lanes per run (splat) or point (slice)
+  static constexpr int NG = NT / LPR;
+  static constexpr int UPT = 8;             // lattice rows staged per thread in the slice
+  static constexpr int RC = UPT * NT / G;   // lattice rows per slice chunk
+  static constexpr int PPG = (kPts + NG - 1) / NG;  // points per lane group in the slice
+  // LDS row stride in elements: rows of 64 bytes or more get 16 bytes of
+  // padding, so lane groups reading different rows spread over the banks
+  static constexpr int RS = G * (int)sizeof(TU) >= 64 ? G + 16 / (int)sizeof(TU) : G;
+  // point values can be staged as whole 16-byte vectors per thread
+  static constexpr bool VEC = VPT >= Vec16<TU>::N && VPT % Vec16<TU>::N == 0;
+};
+
+// LDS layout of k_splat_tile: values [P][G] (TU) | weights [P*D] (fp32) |
+// partial rows [maxq] (int32) | run starts [maxq+1] (uint16) | entry points
+// [P*D] (uint8) | next unclaimed run (int32).
+struct SplatLds {
+  size_t w, dst, rel, lp, next, total;
+};
+template <typename TU>
+__host__ __device__ inline SplatLds splat_lds(int P, int D, int maxq, int G) {
+  SplatLds o;
+  const int rs = G * (int)sizeof(TU) >= 64 ? G + 16 / (int)sizeof(TU) : G;
+  size_t b = sizeof(TU) * (size_t)P * rs;
+  o.w = b;
+  b += sizeof(float) * (size_t)P * D;
+  o.dst = b;
+  b += sizeof(int32_t) * (size_t)maxq;
+  o.rel = b;
+  b += sizeof(uint16_t) * (size_t)(maxq + 1);
+  b = (b + 3) & ~(size_t)3;
+  o.lp = b;
+  b += ((size_t)P * D + 3) & ~(size_t)3;
+  o.next = b;
+  b += sizeof(int);
+  o.total = (b + 15) & ~(size_t)15;
+  return o;
 }
 
-template <typename TV, typename TU, int G>
-__global__ __launch_bounds__(kBlock) void k_splat_tile(const int32_t* __restrict__ tile_off,
-                                                       const uint16_t* __restrict__ run_rel,
-                                                       const uint8_t* __restrict__ ent_lp,
-                                                       const float* __restrict__ ent_w,
-                                                       const TV* __restrict__ V,
-                                                       const uint32_t* __restrict__ perm,
-                                                       TU* __restrict__ part, int64_t n, int P, int D,
-                                                       int C, int stage_v) {
+// Scalars of k_splat_tile; its arrays are separate non-aliasing kernel
+// arguments, so uniform loads (tile offsets) go through the scalar cache
+// and never wait behind the tile's vector loads.
+template <typename TU>
+struct SplatArgs {
+  int64_t n;
+  int64_t items;  // tiles x channel chunks
+  int P, D, C, chunks;
+  int vec_v;  // V rows of a tile are one contiguous run of 16-byte vectors
+  int cvec;   // rows of C channels start 16-byte aligned
+  SplatLds lds;
+};
+
+// W^T restricted to one tile (Section 3.2, Splat). The block stages the
+// tile's values, entries and run lists in LDS from registers that were
+// loaded while the previous tile was being reduced. Each run (one lattice
+// point of the tile) is summed by LPR lanes of VW channels, entries in
+// order; a lane group that finishes a run claims the next unclaimed one, so
+// runs of different lengths balance over the groups. The sum lands in the
+// lattice point's block of partial rows (run_dst).
+template <typename TU, int G>
+__global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_splat_tile(
+    const int32_t* __restrict__ tile_off, const uint16_t* __restrict__ run_rel,
+    const int32_t* __restrict__ run_dst, const uint8_t* __restrict__ ent_lp,
+    const float* __restrict__ ent_w, const TU* __restrict__ V, const uint32_t* __restrict__ perm,
+    TU* __restrict__ part, SplatArgs<TU> a) {
+  using S = TileShape<TU, G, kSplatBlock>;
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int R = kBlock / G;
-  const int lane = threadIdx.x % G, row = threadIdx.x / G;
-  const int64_t t = blockIdx.x;
-  const int c = blockIdx.y * G + lane;
-  const bool cv = c < C;
-  const int64_t p0 = t * P;
-  const int np = (int)(n - p0 < P ? n - p0 : P);
-  const int ne = np * D;
-  const int64_t ebase = p0 * D;
-  const int q0 = tile_off[t], nq = tile_off[t + 1] - q0;
   TU* lv = (TU*)smem;
-  float* lw = (float*)(lv + (size_t)(stage_v ? P : 0) * G);
-  uint16_t* lrel = (uint16_t*)(lw + (size_t)P * D);
-  uint8_t* llp = (uint8_t*)(((uintptr_t)(lrel + nq + 1) + 3) & ~(uintptr_t)3);
-  // stage the tile: its points' values, its entries and its run starts.
-  // Every load of a thread is issued before any LDS store, so the loads of
-  // one thread are in flight together.
-  if (stage_v) {
-    // np <= P <= R * G: at most G rows per thread
-    TU vt[G];
+  float* lw = (float*)(smem + a.lds.w);
+  int32_t* ldst = (int32_t*)(smem + a.lds.dst);
+  uint16_t* lrel = (uint16_t*)(smem + a.lds.rel);
+  uint8_t* llp = smem + a.lds.lp;
+  int* lnext = (int*)(smem + a.lds.next);
+  const int tid = threadIdx.x;
+  constexpr int N = Vec16<TU>::N;
+
+  TU v[S::VPT];
+  float w[S::EPT];
+  uint32_t lp4[S::EPT / 4];  // entry points, four per register
+  uint16_t rel[S::RPT];
+  int32_t dst[S::RPT];
+  int nq = 0, ne = 0, q0 = 0;
+  // Every load below is unconditional (indices clamped into the tile), so
+  // the whole tile is in flight at once.
+  auto fetch = [&](int64_t item) {
+    const int64_t t = item / a.chunks;
+    const int ch = (int)(item - t * a.chunks);
+    const int64_t p0 = t * a.P;
+    const int np = (int)(a.n - p0 < a.P ? a.n - p0 : a.P);
+    ne = np * a.D;
+    q0 = tile_off[t];
+    nq = tile_off[t + 1] - q0;
+    if (S::VEC && a.vec_v) {
+      const typename Vec16<TU>::T* src = (const typename Vec16<TU>::T*)(V + p0 * a.C);
+      const int nvec = np * G / N;
 #pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const int lp = row + i * R;
-      vt[i] = 0;
-      if (lp < np && cv) {
-        const int64_t pt = p0 + lp;
+      for (int u = 0; u < S::VPT / N; ++u) {
+        const int vi = tid + u * kSplatBlock;
+        const typename Vec16<TU>::T x = src[vi < nvec ? vi : nvec - 1];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[u * N + j] = x[j];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < S::VPT; ++u) {
+        const int f = tid + u * kSplatBlock;
+        const int p = f / G < np ? f / G : np - 1;
+        const int c = ch * G + f % G;
+        const int64_t pt = p0 + p;
         const int64_t src = perm ? (int64_t)perm[pt] : pt;
-        vt[i] = (TU)V[src * C + c];
+        v[u] = V[src * a.C + (c < a.C ? c : a.C - 1)];
+      }
+    }
+    const float* gw = ent_w + p0 * a.D;
+#pragma unroll
+    for (int u = 0; u < S::EPT; ++u) {
+      const int e = tid + u * kSplatBlock;
+      w[u] = gw[e < ne ? e : ne - 1];
+    }
+    // the tile starts 4-byte aligned (P is a multiple of 4) and the array
+    // has spare bytes past its end
+    const uint32_t* glp4 = (const uint32_t*)(ent_lp + p0 * a.D);
+    const int nw = (ne + 3) / 4;
+#pragma unroll
+    for (int u = 0; u < S::EPT / 4; ++u) {
+      const int wi = tid + u * kSplatBlock;
+      lp4[u] = glp4[wi < nw ? wi : nw - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < S::RPT; ++u) {
+      const int q = tid + u * kSplatBlock;
+      rel[u] = run_rel[q0 + (q < nq ? q : nq - 1)];
+      dst[u] = run_dst[q0 + (q < nq ? q : nq - 1)];
+    }
+  };
+
+  int64_t item, end, step;
+  xcd_items(a.items, &item, &end, &step);
+  if (item < end) fetch(item);
+  for (; item < end; item += step) {
+    const int cur_nq = nq, cur_ne = ne, cur_q0 = q0;
+    __syncthreads();  // the previous tile's runs are done with the LDS
+    if (S::VEC && a.vec_v) {
+#pragma unroll
+      for (int u = 0; u < S::VPT / N; ++u) {
+        const int vi = tid + u * kSplatBlock;
+        if (vi * N < cur_ne / a.D * G) {
+          typename Vec16<TU>::T x;
+#pragma unroll
+          for (int j = 0; j < N; ++j) x[j] = v[u * N + j];
+          const int f = vi * N;  // N consecutive elements of one row
+          *(typename Vec16<TU>::T*)(lv + (f / G) * S::RS + f % G) = x;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < S::VPT; ++u) {
+        const int f = tid + u * kSplatBlock;
+        if (f < cur_ne / a.D * G) lv[(f / G) * S::RS + f % G] = v[u];
       }
     }
 #pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const int lp = row + i * R;
-      if (lp < np) lv[lp * G + lane] = vt[i];
+    for (int u = 0; u < S::EPT; ++u) {
+      const int e = tid + u * kSplatBlock;
+      if (e < cur_ne) lw[e] = w[u];
     }
-  }
-  stage_entries(ent_w + ebase, ent_lp + ebase, ne, lw, llp);
-  for (int i = threadIdx.x; i < nq; i += kBlock) lrel[i] = run_rel[q0 + i];
-  if (threadIdx.x == 0) lrel[nq] = (uint16_t)ne;
-  __syncthreads();
-  // one run (= one lattice point of this tile) per G lanes, entries in order
-  for (int qq = row; qq < nq; qq += R) {
-    TU acc = 0;
-    const int e1 = lrel[qq + 1];
-    if (stage_v) {
-      int e = lrel[qq];
-      for (; e + 4 <= e1; e += 4) {
-        int lp[4];
-        float wv[4];
+#pragma unroll
+    for (int u = 0; u < S::EPT / 4; ++u) {
+      const int wi = tid + u * kSplatBlock;
+      if (4 * wi < cur_ne) ((uint32_t*)llp)[wi] = lp4[u];
+    }
+#pragma unroll
+    for (int u = 0; u < S::RPT; ++u) {
+      const int q = tid + u * kSplatBlock;
+      if (q < cur_nq) {
+        lrel[q] = rel[u];
+        ldst[q] = dst[u];
+      }
+    }
+    // runs past the prefetched ones (tiles with very many distinct points)
+    for (int q = S::RPT * kSplatBlock + tid; q < cur_nq; q += kSplatBlock) {
+      lrel[q] = run_rel[cur_q0 + q];
+      ldst[q] = run_dst[cur_q0 + q];
+    }
+    if (tid == 0) {
+      lrel[cur_nq] = (uint16_t)cur_ne;
+      *lnext = S::NG;  // runs 0 .. NG-1 start on their own group
+    }
+    __syncthreads();
+    if (item + step < end) fetch(item + step);  // in flight while this tile is reduced
+
+    const int ch = (int)(item % a.chunks);
+    const int grp = tid / S::LPR;
+    const int cg = ch * G + (tid % S::LPR) * S::VW;
+    const bool full = cg + S::VW <= a.C;
+    int q = grp;
+    if (q < cur_nq && cg < a.C) {
+      int e = lrel[q], e1 = lrel[q + 1];
+      int dq = ldst[q];
+      TU acc[S::VW];
+#pragma unroll
+      for (int i = 0; i < S::VW; ++i) acc[i] = 0;
+      for (;;) {
+        // up to four entries of the run per pass, added in entry order
+        const int cnt = e1 - e < 4 ? e1 - e : 4;
+        int lpu[4];
+        TU wu[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          lp[u] = llp[e + u];
-          wv[u] = lw[e + u];
+          const int eu = e + (u < cnt ? u : cnt - 1);
+          lpu[u] = (int)llp[eu];
+          wu[u] = (TU)lw[eu];
         }
-        TU v[4];
+        TU x[4][S::VW];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = lv[lp[u] * G + lane];
+        for (int u = 0; u < 4; ++u) read_row<TU, S::VW>(lv + lpu[u] * S::RS + (cg - ch * G), x[u]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = fma_t((TU)wv[u], v[u], acc);
-      }
-      for (; e < e1; ++e) acc = fma_t((TU)lw[e], lv[(int)llp[e] * G + lane], acc);
-    } else if (cv) {
-      for (int e = lrel[qq]; e < e1; ++e) {
-        const int64_t pt = p0 + llp[e];
-        const int64_t src = perm ? (int64_t)perm[pt] : pt;
-        acc = fma_t((TU)lw[e], (TU)V[src * C + c], acc);
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < S::VW; ++i) acc[i] = u < cnt ? fma_t(wu[u], x[u][i], acc[i]) : acc[i];
+        e += cnt - 1;
+        if (++e == e1) {
+          TU* o = part + (int64_t)dq * a.C + cg;
+          if (full && a.cvec) {
+            write_row<TU, S::VW>(o, acc);
+          } else {
+#pragma unroll
+            for (int i = 0; i < S::VW; ++i)
+              if (cg + i < a.C) o[i] = acc[i];
+          }
+          // next run: whichever is unclaimed (one group's lanes share it);
+          // a run's sum does not depend on which group takes it
+          int nx = 0;
+          if (tid % S::LPR == 0) nx = atomicAdd(lnext, 1);
+          q = __shfl(nx, tid - tid % S::LPR);
+          if (q >= cur_nq) break;
+          e = lrel[q];
+          e1 = lrel[q + 1];
+          dq = ldst[q];
+#pragma unroll
+          for (int i = 0; i < S::VW; ++i) acc[i] = 0;
+        }
       }
     }
-    if (cv) part[(int64_t)(q0 + qq) * C + c] = acc;
   }
 }
 
-// Lattice point j sums its partial rows; S = G*E lanes per point, E lanes
-// striding its list, combined by a fixed butterfly.
+// Lattice point j sums its partial rows occ_ptr[j] .. occ_ptr[j+1]-1 (one
+// per tile touching it, contiguous); S = G*E lanes per point, E lanes
+// striding the rows, combined by a fixed butterfly.
 template <typename TU, int G>
 __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restrict__ occ_ptr,
-                                                         const int32_t* __restrict__ occ,
                                                          const TU* __restrict__ part,
                                                          TU* __restrict__ U, int64_t m, int C, int E,
                                                          int64_t rows_per_block) {
@@ -186,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restri
     const int o0 = occ_ptr[j], o1 = occ_ptr[j + 1];
     for (int c = c0; c < C; c += G) {
       TU acc = 0;
-      for (int o = o0 + u; o < o1; o += E) acc += part[(int64_t)occ[o] * C + c];
+      for (int o = o0 + u; o < o1; o += E) acc += part[(int64_t)o * C + c];
       for (int off = G; off < S; off <<= 1) acc += __shfl_xor(acc, off);
       if (u == 0) U[j * C + c] = acc;
     }
@@ -250,132 +453,319 @@ __global__ __launch_bounds__(kBlock) void k_blur(BlurArgs<TU> a) {
   }
 }
 
-// LDS layout of k_slice_tile: lattice rows [RC][G] (TU) | weights [P*D]
-// (fp32) | slots [P*D] (uint16).
-template <typename TU>
-__host__ __device__ inline size_t slice_lds_bytes(int P, int D, int RC, int G) {
-  size_t b = sizeof(TU) * (size_t)RC * G;
-  if (b < sizeof(double) * kBlock) b = sizeof(double) * kBlock;  // CG reduction reuses it
+// LDS layout of k_slice_tile: lattice rows [RC][G] (TU; also the CG
+// reduction area) | weights [P*D] (fp32) | slots [P*D] (uint16).
+struct SliceLds {
+  size_t w, sl, total;
+};
+template <typename TU, int G>
+__host__ __device__ inline SliceLds slice_lds(int P, int D, int maxq) {
+  using S = TileShape<TU, G, kSliceBlock>;
+  SliceLds o;
+  size_t b = sizeof(TU) * (size_t)S::RC * S::RS;
+  const size_t red = sizeof(double) * kSliceBlock * S::VW;
+  if (b < red) b = red;
+  o.w = b;
   b += sizeof(float) * (size_t)P * D;
-  b += sizeof(uint16_t) * (size_t)P * D;
-  return (b + 15) & ~(size_t)15;
+  o.sl = b;
+  b += sizeof(uint16_t) * (size_t)(P * D + 1);
+  o.total = (b + 15) & ~(size_t)15;
+  return o;
 }
 
-// The tile's (slot, weight) entries are staged once; its lattice rows are
-// staged RC at a time, and each point adds the entries whose slot falls in
-// the staged chunk. A thread keeps the sums of its ceil(P/R) <= G points.
-template <typename TV, typename TU, int G, bool CG>
-__global__ __launch_bounds__(kBlock) void k_slice_tile(const int32_t* __restrict__ tile_off,
-                                                       const int32_t* __restrict__ tile_verts,
-                                                       const uint16_t* __restrict__ loc,
-                                                       const float* __restrict__ ws,
-                                                       const TU* __restrict__ U,
-                                                       TV* __restrict__ out,
-                                                       const uint32_t* __restrict__ perm, int64_t n,
-                                                       int P, int D, int C, int RC, TU scale, TV noise,
-                                                       const TV* __restrict__ p,
-                                                       double* __restrict__ partials,
-                                                       const uint32_t* __restrict__ mperm,
-                                                       int64_t mrows) {
+// Scalars of k_slice_tile (its arrays are separate non-aliasing kernel
+// arguments, as in k_splat_tile).
+template <typename TU>
+struct SliceArgs {
+  int64_t n;
+  int64_t items;
+  int P, D, C, chunks;
+  int cvec;
+  TU scale;
+  TU noise;
+  int64_t mrows;        // CG: rows whose caller index is >= mrows are not solved for
+  SliceLds lds;
+};
+
+// out = scale * W U restricted to one tile (Section 3.2, Slice). The tile's
+// (slot, weight) entries and its first RC lattice rows arrive in registers
+// while the previous tile is computed; a tile with more runs stages the rest
+// RC rows at a time. Each point is combined by LPR lanes of
+// VW channels from the staged rows. The CG variant adds noise * p and emits
+// the tile's p . out per column, reduced in a fixed order.
+template <typename TU, int G, bool CG>
+// perm: caller row of each sorted point, or null. CG only: p is the
+// direction (sorted order), partials receive each tile's p . out per
+// column, mperm maps sorted points to caller rows for the mrows mask.
+__global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
+    const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_verts,
+    const uint16_t* __restrict__ loc, const float* __restrict__ ws, const TU* __restrict__ U,
+    TU* __restrict__ out, const uint32_t* __restrict__ perm, const TU* __restrict__ p,
+    double* __restrict__ partials, const uint32_t* __restrict__ mperm, SliceArgs<TU> a) {
+  using S = TileShape<TU, G, kSliceBlock>;
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int R = kBlock / G;
-  const int lane = threadIdx.x % G, row = threadIdx.x / G;
-  const int64_t t = xcd_block(blockIdx.x, gridDim.x);
-  const int c = blockIdx.y * G + lane;
-  const bool cv = c < C;
-  const int64_t p0 = t * P;
-  const int np = (int)(n - p0 < P ? n - p0 : P);
-  const int ne = np * D;
-  const int64_t ebase = p0 * D;
-  const int q0 = tile_off[t], nq = tile_off[t + 1] - q0;
-  size_t ub = sizeof(TU) * (size_t)RC * G;
-  if (ub < sizeof(double) * kBlock) ub = sizeof(double) * kBlock;
   TU* lu = (TU*)smem;
-  float* lw = (float*)(smem + ub);
-  uint16_t* lsl = (uint16_t*)(lw + (size_t)P * D);
-  stage_entries(ws + ebase, loc + ebase, ne, lw, lsl);
-  TU acc[G];
+  float* lw = (float*)(smem + a.lds.w);
+  uint16_t* lsl = (uint16_t*)(smem + a.lds.sl);
+  const int tid = threadIdx.x;
+  constexpr int RC = S::RC;
+
+  float w[S::EPT];
+  uint32_t sl2[S::EPT / 2];  // two 16-bit slots per register
+  TU ur[S::UPT];
+  int nq = 0, np = 0, q0 = 0;
+  // rows [r0, r0 + nr) (nr >= 1) of a tile's run list, whose lattice points
+  // are verts[r0 ..]. Indices past the end are clamped to valid ones, so all
+  // index loads issue before the row loads that depend on them.
+  int32_t vj[S::UPT];
+  auto load_index = [&](int r0, int nr, const int32_t* verts) {
 #pragma unroll
-  for (int a = 0; a < G; ++a) acc[a] = 0;
-  for (int r0 = 0; r0 < nq; r0 += RC) {
-    const int nr = nq - r0 < RC ? nq - r0 : RC;
-    __syncthreads();  // previous chunk fully consumed (and entries staged)
-    // eight rows per thread in flight: indices first, then the rows
-    for (int sb = row; sb < nr; sb += 8 * R) {
-      int32_t vj[8];
+    for (int u = 0; u < S::UPT; ++u) {
+      const int r = (tid + u * kSliceBlock) / G;
+      vj[u] = verts[r0 + (r < nr ? r : nr - 1)];
+    }
+  };
+  auto load_rows = [&](int ch) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int sr = sb + u * R;
-        vj[u] = sr < nr ? tile_verts[q0 + r0 + sr] : 0;
-      }
-      TU vr[8];
+    for (int u = 0; u < S::UPT; ++u) {
+      const int c = ch * G + (tid + u * kSliceBlock) % G;
+      ur[u] = U[(int64_t)vj[u] * a.C + (c < a.C ? c : a.C - 1)];
+    }
+  };
+  auto fetch = [&](int64_t item) {
+    const int64_t t = item / a.chunks;
+    const int ch = (int)(item - t * a.chunks);
+    const int64_t p0 = t * a.P;
+    np = (int)(a.n - p0 < a.P ? a.n - p0 : a.P);
+    const int ne = np * a.D;
+    q0 = tile_off[t];
+    nq = tile_off[t + 1] - q0;
+    // row indices first: the rows wait only for them, not for the entries
+    load_index(0, nq < RC ? nq : RC, tile_verts + q0);
+    const float* gw = ws + p0 * a.D;
+    const uint16_t* gsl = loc + p0 * a.D;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int sr = sb + u * R;
-        vr[u] = (sr < nr && cv) ? U[(int64_t)vj[u] * C + c] : (TU)0;
-      }
+    for (int u = 0; u < S::EPT; ++u) {
+      const int e = tid + u * kSliceBlock;
+      w[u] = gw[e < ne ? e : ne - 1];
+    }
+    // slots in pairs (the tile starts 4-byte aligned; the array has a
+    // spare slot past its end)
+    const uint32_t* gsl2 = (const uint32_t*)gsl;
+    const int npair = (ne + 1) / 2;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int sr = sb + u * R;
-        if (sr < nr) lu[sr * G + lane] = vr[u];
+    for (int u = 0; u < S::EPT / 2; ++u) {
+      const int pi = tid + u * kSliceBlock;
+      sl2[u] = gsl2[pi < npair ? pi : npair - 1];
+    }
+    load_rows(ch);
+  };
+  auto stage_rows = [&](int nr) {
+#pragma unroll
+    for (int u = 0; u < S::UPT; ++u) {
+      const int f = tid + u * kSliceBlock;
+      if (f < nr * G) lu[(f / G) * S::RS + f % G] = ur[u];
+    }
+  };
+
+  int64_t item, end, step;
+  xcd_items(a.items, &item, &end, &step);
+  if (item < end) fetch(item);
+  for (; item < end; item += step) {
+    const int64_t t = item / a.chunks;
+    const int ch = (int)(item - t * a.chunks);
+    const int cur_nq = nq, cur_np = np, cur_ne = np * a.D, cur_q0 = q0;
+    __syncthreads();  // the previous tile is done with the LDS
+#pragma unroll
+    for (int u = 0; u < S::EPT; ++u) {
+      const int e = tid + u * kSliceBlock;
+      if (e < cur_ne) lw[e] = w[u];
+    }
+#pragma unroll
+    for (int u = 0; u < S::EPT / 2; ++u) {
+      const int pi = tid + u * kSliceBlock;
+      if (2 * pi < cur_ne) ((uint32_t*)lsl)[pi] = sl2[u];
+    }
+    stage_rows(cur_nq < RC ? cur_nq : RC);
+
+    const int grp = tid / S::LPR;
+    const int cl = (tid % S::LPR) * S::VW;  // channel offset within the chunk
+    const int cg = ch * G + cl;
+    const bool live = cg < a.C;
+    const bool full = cg + S::VW <= a.C;
+    // CG: this thread's p values, requested before the next tile's loads
+    // so that using them never waits for those
+    TU pv[S::PPG][S::VW];
+#pragma unroll
+    for (int k = 0; k < S::PPG; ++k) {
+      const int lp = grp + k * S::NG;
+#pragma unroll
+      for (int i = 0; i < S::VW; ++i) pv[k][i] = 0;
+      if (CG && lp < cur_np && live) {
+        const int64_t pt = t * a.P + lp;
+        const TU* src = p + pt * a.C + cg;
+        if (full && a.cvec) {
+          read_row<TU, S::VW>(src, pv[k]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < S::VW; ++i)
+            if (cg + i < a.C) pv[k][i] = src[i];
+        }
       }
     }
-    __syncthreads();
+    TU acc[S::PPG][S::VW];
 #pragma unroll
-    for (int a = 0; a < G; ++a) {
-      const int lp = a * R + row;
-      if (lp < np) {
-        const int eb = lp * D;
-        int k = 0;
-        for (; k + 4 <= D; k += 4) {
-          int sl[4];
-          float wv[4];
+    for (int k = 0; k < S::PPG; ++k)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            sl[u] = (int)lsl[eb + k + u] - r0;
-            wv[u] = lw[eb + k + u];
+      for (int i = 0; i < S::VW; ++i) acc[k][i] = 0;
+    for (int r0 = 0; r0 < cur_nq; r0 += RC) {
+      const int nr = cur_nq - r0 < RC ? cur_nq - r0 : RC;
+      if (r0 > 0) {
+        __syncthreads();  // previous chunk consumed
+        load_index(r0, nr, tile_verts + cur_q0);
+        load_rows(ch);
+        stage_rows(nr);
+      }
+      __syncthreads();
+      // the next tile's entries and first rows load during the last chunk
+      if (r0 + RC >= cur_nq && item + step < end) fetch(item + step);
+      if (live) {
+#pragma unroll
+        for (int k = 0; k < S::PPG; ++k) {
+          const int lp = grp + k * S::NG;
+          if (lp < cur_np) {
+            const int eb = lp * a.D;
+            // EB entries at a time: slots and weights, then their rows
+            constexpr int EB = S::VW * sizeof(TU) >= 32 ? 2 : 4;
+            for (int j0 = 0; j0 < a.D; j0 += EB) {
+              int sv[EB];
+              TU wv[EB];
+#pragma unroll
+              for (int u = 0; u < EB; ++u) {
+                const int j = j0 + u < a.D ? j0 + u : a.D - 1;
+                sv[u] = (int)lsl[eb + j] - r0;
+                wv[u] = (TU)lw[eb + j];
+              }
+              TU x[EB][S::VW];
+#pragma unroll
+              for (int u = 0; u < EB; ++u) {
+                const bool in = (unsigned)sv[u] < (unsigned)nr;
+                read_row<TU, S::VW>(lu + (in ? sv[u] : 0) * S::RS + cl, x[u]);
+              }
+#pragma unroll
+              for (int u = 0; u < EB; ++u) {
+                const bool in = (unsigned)sv[u] < (unsigned)nr && j0 + u < a.D;
+#pragma unroll
+                for (int i = 0; i < S::VW; ++i) acc[k][i] = in ? fma_t(wv[u], x[u][i], acc[k][i]) : acc[k][i];              }
+            }
           }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if ((unsigned)sl[u] < (unsigned)nr) acc[a] = fma_t((TU)wv[u], lu[sl[u] * G + lane], acc[a]);
-        }
-        for (; k < D; ++k) {
-          const int sl = (int)lsl[eb + k] - r0;
-          if ((unsigned)sl < (unsigned)nr) acc[a] = fma_t((TU)lw[eb + k], lu[sl * G + lane], acc[a]);
         }
       }
     }
-  }
-  double dot = 0.0;
+    double dot[S::VW];
 #pragma unroll
-  for (int a = 0; a < G; ++a) {
-    const int lp = a * R + row;
-    if (lp < np && cv) {
-      const int64_t pt = p0 + lp;
-      TV o = (TV)(scale * acc[a]);
-      if (CG) {
-        const TV pv = p[pt * C + c];
-        o = fma_t(noise, pv, o);
-        if (mrows > 0 && (int64_t)mperm[pt] >= mrows) o = 0;  // not solved for
-        dot += (double)pv * (double)o;
+    for (int i = 0; i < S::VW; ++i) dot[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < S::PPG; ++k) {
+      const int lp = grp + k * S::NG;
+      if (lp < cur_np && live) {
+        const int64_t pt = t * a.P + lp;
+        TU o[S::VW];
+        const bool masked = CG && a.mrows > 0 && (int64_t)mperm[pt] >= a.mrows;  // not solved for
+#pragma unroll
+        for (int i = 0; i < S::VW; ++i) {
+          o[i] = a.scale * acc[k][i];
+          if (CG) {
+            o[i] = masked ? (TU)0 : fma_t(a.noise, pv[k][i], o[i]);
+            dot[i] += (double)pv[k][i] * (double)o[i];
+          }
+        }
+        TU* dstp = out + (perm ? (int64_t)perm[pt] : pt) * a.C + cg;
+        if (full && a.cvec) {
+          write_row<TU, S::VW>(dstp, o);
+        } else {
+#pragma unroll
+          for (int i = 0; i < S::VW; ++i)
+            if (cg + i < a.C) dstp[i] = o[i];
+        }
       }
-      out[(perm ? (int64_t)perm[pt] : pt) * C + c] = o;
     }
-  }
-  if (CG) {
-    __syncthreads();
-    double* sh = (double*)smem;
-    sh[threadIdx.x] = dot;
-    __syncthreads();
-    if ((int)threadIdx.x < G && cv) {
-      double s = 0.0;
-      for (int rr = 0; rr < R; ++rr) s += sh[rr * G + threadIdx.x];
-      partials[t * C + c] = s;
+    if (CG) {
+      // per column: groups' sums in a fixed two-level order
+      __syncthreads();  // every lane is done with the staged rows
+      double* sh = (double*)smem;
+#pragma unroll
+      for (int i = 0; i < S::VW; ++i) sh[tid * S::VW + i] = dot[i];
+      __syncthreads();
+      // thread (c, s): channel c of the chunk, groups s, s + 16, ...
+      constexpr int SPLIT = kSliceBlock / G < 16 ? kSliceBlock / G : 16;
+      double part2 = 0.0;
+      if (tid < G * SPLIT) {
+        const int c = tid % G, sidx = tid / G;
+        const int lane_in = c / S::VW, i = c % S::VW;
+        for (int g = sidx; g < S::NG; g += SPLIT) part2 += sh[(g * S::LPR + lane_in) * S::VW + i];
+      }
+      __syncthreads();
+      if (tid < G * SPLIT) sh[tid] = part2;
+      __syncthreads();
+      if (tid < G && ch * G + tid < a.C) {
+        double s = 0.0;
+        for (int sidx = 0; sidx < SPLIT; ++sidx) s += sh[sidx * G + tid];
+        partials[t * a.C + ch * G + tid] = s;
+      }
     }
   }
 }
 
-int slice_rows_per_chunk(const sgp_lattice* L, int G, size_t elem);
+
+template <typename TU>
+size_t slice_lds_g(int P, int D, int maxq, int g) {
+  switch (g) {
+    case 1: return slice_lds<TU, 1>(P, D, maxq).total;
+    case 2: return slice_lds<TU, 2>(P, D, maxq).total;
+    case 4: return slice_lds<TU, 4>(P, D, maxq).total;
+    case 8: return slice_lds<TU, 8>(P, D, maxq).total;
+    case 16: return slice_lds<TU, 16>(P, D, maxq).total;
+    case 32: return slice_lds<TU, 32>(P, D, maxq).total;
+    default: return slice_lds<TU, 64>(P, D, maxq).total;
+  }
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int cu_count() {
+  constexpr int kMaxDevices = 64;
+  static int cus[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
+  if (!cus[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 256;
+    cus[dev] = c;
+  }
+  return cus[dev];
+}
+
+// Blocks of a persistent tile kernel: as many as can be resident, at most
+// one per work item. A kernel staging more than 64 KiB of LDS is first
+// allowed to.
+unsigned persistent_grid(const void* kernel, int threads, size_t lds, int64_t items) {
+  if (lds > 65536) (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipGetLastError();
+  int bpc = tuning().blocks_per_cu;
+  if (bpc <= 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    bpc = nb;
+  }
+  int64_t g = (int64_t)cu_count() * bpc;
+  if (g > items) g = items;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
 
 // Blocks for `rows` rows at R per block, capped, and the rows each block
 // takes so that the blocks cover all rows.
@@ -387,9 +777,9 @@ void split_rows(int64_t rows, int R, int64_t cap, unsigned* blocks, int64_t* row
   *blocks = (unsigned)((rows + *rows_per_block - 1) / *rows_per_block);
 }
 
-template <typename TV, typename TU, int G>
-int mvm_g(const sgp_lattice* L, const TV* V, const uint32_t* perm, int C, TV* out, hipStream_t s,
-          TV noise, const TV* p, double* partials) {
+template <typename TU, int G>
+int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out, hipStream_t s,
+          TU noise, const TU* p, double* partials) {
   const int d = L->d, D = d + 1, T = 2 * L->order;
   const int64_t m = L->m, mC = m * C;
   TU* U0 = (TU*)L->ubuf.ptr;
@@ -400,14 +790,24 @@ int mvm_g(const sgp_lattice* L, const TV* V, const uint32_t* perm, int C, TV* ou
   const int chunks = (C + G - 1) / G;
   const int P = L->tile_points;
   const dim3 tgrid((unsigned)L->ntiles, (unsigned)chunks);
+  const int maxq = L->max_tile_runs;
   {
     ProfScope ps(KK_SPLAT, s);
-    const bool stage_v = tuning().splat_stage_v != 0;
-    const size_t lds = splat_lds_bytes<TU>(P, D, L->max_tile_runs, G, stage_v);
-    hipLaunchKernelGGL((k_splat_tile<TV, TU, G>), tgrid, dim3(kBlock), lds, s,
+    SplatArgs<TU> sa;
+    sa.n = L->n;
+    sa.items = L->ntiles * chunks;
+    sa.P = P;
+    sa.D = D;
+    sa.C = C;
+    sa.chunks = chunks;
+    sa.vec_v = (TileShape<TU, G, kSplatBlock>::VEC && !perm && C == G && aligned16(V)) ? 1 : 0;
+    sa.cvec = (C % Vec16<TU>::N == 0 && aligned16(part)) ? 1 : 0;
+    sa.lds = splat_lds<TU>(P, D, maxq, G);
+    const unsigned grid = persistent_grid((const void*)&k_splat_tile<TU, G>, kSplatBlock, sa.lds.total, sa.items);
+    hipLaunchKernelGGL((k_splat_tile<TU, G>), dim3(grid), dim3(kSplatBlock), sa.lds.total, s,
                        (const int32_t*)L->tile_off.ptr, (const uint16_t*)L->run_rel.ptr,
-                       (const uint8_t*)L->ent_lp.ptr, (const float*)L->ent_w.ptr, V, perm, part, L->n,
-                       P, D, C, stage_v ? 1 : 0);
+                       (const int32_t*)L->run_dst.ptr, (const uint8_t*)L->ent_lp.ptr,
+                       (const float*)L->ent_w.ptr, V, perm, part, sa);
     SGP_LAUNCH_CHECK("k_splat_tile");
   }
   {
@@ -420,8 +820,7 @@ int mvm_g(const sgp_lattice* L, const TV* V, const uint32_t* perm, int C, TV* ou
     int64_t rpb;
     split_rows(m, kBlock / (G * E), 65536, &blocks, &rpb);
     hipLaunchKernelGGL((k_splat_gather<TU, G>), dim3(blocks), dim3(kBlock), 0, s,
-                       (const int32_t*)L->occ_ptr.ptr, (const int32_t*)L->occ.ptr, part, U0, m, C, E,
-                       rpb);
+                       (const int32_t*)L->occ_ptr.ptr, part, U0, m, C, E, rpb);
     SGP_LAUNCH_CHECK("k_splat_gather");
   }
 
@@ -459,85 +858,84 @@ int mvm_g(const sgp_lattice* L, const TV* V, const uint32_t* perm, int C, TV* ou
   }
   const TU scale = sym ? (TU)(0.5 * (double)L->outputscale) : (TU)L->outputscale;
   ProfScope ps(KK_SLICE, s);
-  const int RC = slice_rows_per_chunk(L, G, sizeof(TU));
-  const size_t lds = slice_lds_bytes<TU>(P, D, RC, G);
+  SliceArgs<TU> la;
+  la.n = L->n;
+  la.items = L->ntiles * chunks;
+  la.P = P;
+  la.D = D;
+  la.C = C;
+  la.chunks = chunks;
+  la.cvec = (C % Vec16<TU>::N == 0 && aligned16(out) && (!p || aligned16(p))) ? 1 : 0;
+  la.scale = scale;
+  la.noise = noise;
+  la.mrows = partials ? L->solve_rows : 0;
+  la.lds = slice_lds<TU, G>(P, D, maxq);
+  const int32_t* toff = (const int32_t*)L->tile_off.ptr;
+  const int32_t* tverts = (const int32_t*)L->tile_verts.ptr;
+  const uint16_t* loc = (const uint16_t*)L->loc.ptr;
+  const float* ws = (const float*)L->ws.ptr;
+  const uint32_t* mperm = (const uint32_t*)L->perm.ptr;
   if (partials) {
-    hipLaunchKernelGGL((k_slice_tile<TV, TU, G, true>), tgrid, dim3(kBlock), lds, s,
-                       (const int32_t*)L->tile_off.ptr, (const int32_t*)L->tile_verts.ptr,
-                       (const uint16_t*)L->loc.ptr, (const float*)L->ws.ptr, cur[0], out, perm,
-                       L->n, P, D, C, RC, scale, noise, p, partials, (const uint32_t*)L->perm.ptr,
-                       L->solve_rows);
+    const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, true>, kSliceBlock, la.lds.total, la.items);
+    hipLaunchKernelGGL((k_slice_tile<TU, G, true>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
+                       tverts, loc, ws, (const TU*)cur[0], out, perm, p, partials, mperm, la);
   } else {
-    hipLaunchKernelGGL((k_slice_tile<TV, TU, G, false>), tgrid, dim3(kBlock), lds, s,
-                       (const int32_t*)L->tile_off.ptr, (const int32_t*)L->tile_verts.ptr,
-                       (const uint16_t*)L->loc.ptr, (const float*)L->ws.ptr, cur[0], out, perm,
-                       L->n, P, D, C, RC, scale, (TV)0, (const TV*)nullptr, nullptr,
-                       (const uint32_t*)nullptr, (int64_t)0);
+    const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, false>, kSliceBlock, la.lds.total, la.items);
+    hipLaunchKernelGGL((k_slice_tile<TU, G, false>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
+                       tverts, loc, ws, (const TU*)cur[0], out, perm, (const TU*)nullptr, (double*)nullptr,
+                       mperm, la);
   }
   SGP_LAUNCH_CHECK("k_slice_tile");
   return SGP_OK;
 }
 
-// Lattice rows per staged chunk in the slice: what the LDS budget leaves
-// after the tile's entries, at most the longest run list.
-int slice_rows_per_chunk(const sgp_lattice* L, int G, size_t elem) {
-  const size_t ent = (sizeof(float) + sizeof(uint16_t)) * (size_t)L->tile_points * (L->d + 1);
-  const size_t budget = (size_t)tuning().lds_budget;
-  const size_t room = budget > ent ? budget - ent : 0;
-  int64_t rc = (int64_t)(room / (elem * G));
-  if (rc > L->max_tile_runs) rc = L->max_tile_runs;
-  if (tuning().slice_rows > 0 && rc > tuning().slice_rows) rc = tuning().slice_rows;
-  return rc < 1 ? 1 : (int)rc;
-}
-
-// Channel chunk: the widest power of two <= 64 covering C for which the
-// splat's staged tile fits the LDS budget and the slice stages at least 64
-// lattice rows (or all of a tile's rows) per chunk.
+// Channel chunk: the widest power of two <= 64 covering C for which both
+// tile kernels' LDS stages fit the budget.
 int chunk_lanes(const sgp_lattice* L, int C, size_t elem) {
   int g = lanes_for(C);
-  const int D = L->d + 1, P = L->tile_points;
+  const int D = L->d + 1, P = L->tile_points, maxq = L->max_tile_runs;
+  const size_t budget = (size_t)tuning().lds_budget;
+  const size_t slice_budget = (size_t)tuning().slice_lds_budget;
   while (g > 1) {
-    const bool sv = tuning().splat_stage_v != 0;
-    const size_t splat = elem == 8 ? splat_lds_bytes<double>(P, D, L->max_tile_runs, g, sv)
-                                   : splat_lds_bytes<float>(P, D, L->max_tile_runs, g, sv);
-    const int rc = slice_rows_per_chunk(L, g, elem);
-    if (splat <= (size_t)tuning().lds_budget && (rc >= 64 || rc >= L->max_tile_runs)) break;
+    const size_t splat = elem == 8 ? splat_lds<double>(P, D, maxq, g).total : splat_lds<float>(P, D, maxq, g).total;
+    const size_t slice = elem == 8 ? slice_lds_g<double>(P, D, maxq, g) : slice_lds_g<float>(P, D, maxq, g);
+    if (splat <= budget && slice <= slice_budget) break;
     g >>= 1;
   }
   return g;
 }
 
-template <typename TV, typename TU>
-int mvm_dispatch(const sgp_lattice* L, const TV* V, const uint32_t* perm, int C, TV* out,
-                 hipStream_t s, TV noise, const TV* p, double* partials) {
+template <typename TU>
+int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out,
+                 hipStream_t s, TU noise, const TU* p, double* partials) {
   int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf,
                        sizeof(TU) * (4 * L->m + L->nrun) * (size_t)C, s);
   if (rc) return rc;
   switch (chunk_lanes(L, C, sizeof(TU))) {
-    case 1: return mvm_g<TV, TU, 1>(L, V, perm, C, out, s, noise, p, partials);
-    case 2: return mvm_g<TV, TU, 2>(L, V, perm, C, out, s, noise, p, partials);
-    case 4: return mvm_g<TV, TU, 4>(L, V, perm, C, out, s, noise, p, partials);
-    case 8: return mvm_g<TV, TU, 8>(L, V, perm, C, out, s, noise, p, partials);
-    case 16: return mvm_g<TV, TU, 16>(L, V, perm, C, out, s, noise, p, partials);
-    case 32: return mvm_g<TV, TU, 32>(L, V, perm, C, out, s, noise, p, partials);
-    default: return mvm_g<TV, TU, 64>(L, V, perm, C, out, s, noise, p, partials);
+    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, partials);
+    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, p, partials);
+    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, p, partials);
+    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, p, partials);
+    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, p, partials);
+    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, p, partials);
+    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, p, partials);
   }
 }
 
 }  // namespace
 
 int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s) {
-  return mvm_dispatch<float, float>(L, V, (const uint32_t*)L->perm.ptr, C, out, s, 0.f, nullptr,
+  return mvm_dispatch<float>(L, V, (const uint32_t*)L->perm.ptr, C, out, s, 0.f, nullptr,
                                     nullptr);
 }
 
 int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t s, double noise,
            double* partials) {
-  return mvm_dispatch<double, double>(L, p, nullptr, C, q, s, noise, p, partials);
+  return mvm_dispatch<double>(L, p, nullptr, C, q, s, noise, p, partials);
 }
 
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s) {
-  return mvm_dispatch<double, double>(L, V, nullptr, C, out, s, 0.0, nullptr, nullptr);
+  return mvm_dispatch<double>(L, V, nullptr, C, out, s, 0.0, nullptr, nullptr);
 }
 
 }  // namespace sgp

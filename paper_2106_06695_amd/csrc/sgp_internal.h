@@ -11,19 +11,19 @@
 
 namespace sgp {
 
-constexpr int kBlock = 256;     // threads per block for every kernel
+constexpr int kBlock = 256;     // threads per block, except the tile kernels
 constexpr int kMaxD = 32;       // largest input dimension
 constexpr int kMaxOrder = 8;    // largest stencil half-width r
 constexpr int kMaxCgCols = 64;  // columns per cg_solve call
 constexpr int kRedBlocks = 512; // blocks (and partial sums) of the reducing vector kernels
 
 // Launch-shape knobs of the MVM kernels. Defaults are the measured best on
-// MI355X; SGP_LDS_BUDGET, SGP_SLICE_ROWS and SGP_SPLAT_STAGE_V in the
-// environment override them (read once per process).
+// MI355X; SGP_LDS_BUDGET, SGP_SLICE_LDS_BUDGET and SGP_TILE_BLOCKS_PER_CU in
+// the environment override them (read once per process).
 struct Tuning {
-  int lds_budget;     // bytes of LDS a tile kernel may stage
-  int slice_rows;     // cap on lattice rows per staged slice chunk (0 = budget only; default 128)
-  int splat_stage_v;  // 1: splat stages the tile's values in LDS; 0: reads them from memory
+  int lds_budget;        // bytes of LDS the splat may stage (one block per CU)
+  int slice_lds_budget;  // bytes of LDS the slice may stage (one block per CU)
+  int blocks_per_cu;     // resident blocks per CU of the persistent tile kernels (0 = occupancy)
 };
 const Tuning& tuning();
 
@@ -65,6 +65,13 @@ enum KernelKind {
   KK_ORDER,
   KK_NUM
 };
+
+// True while the event profiler is enabled.
+bool profiling();
+// Process-wide switch for graph replay of CG iterations.
+bool cg_graphs_enabled();
+// A per-thread, per-device stream used only to record graphs.
+hipStream_t capture_stream();
 
 // Brackets one launch with events when profiling is on (no-op otherwise).
 class ProfScope {
@@ -142,8 +149,9 @@ struct sgp_lattice {
   sgp::DevBuf run_rel;    // nrun uint16: first entry of each run, relative to its tile's entries
   sgp::DevBuf ent_lp;     // n(d+1) uint8: point within its tile, entries grouped by run
   sgp::DevBuf ent_w;      // n(d+1) fp32: weight of each entry, grouped by run
-  sgp::DevBuf occ_ptr;    // m+1 int32: runs of each lattice point in occ
-  sgp::DevBuf occ;        // nrun int32: run indices grouped by lattice point (ascending)
+  sgp::DevBuf occ_ptr;    // m+1 int32: first partial row of each lattice point
+  sgp::DevBuf run_dst;    // nrun int32: partial row of each run; a lattice point's runs
+                          //   occupy rows occ_ptr[j] .. occ_ptr[j+1]-1 in ascending run order
   sgp::DevBuf nbr;        // (d+1) x 2r x m int32: [direction][offset][internal vertex]
   sgp::DevBuf int2can;    // m int32: internal vertex -> canonical index
   sgp::DevBuf keys;       // m x d int32 in canonical order (first occurrence in caller's order)

@@ -173,6 +173,18 @@ def test_cg_fixed_iterations(sgp, orc):
     np.testing.assert_allclose(rel, relo, rtol=1e-3)
 
 
+@pytest.mark.parametrize("C,d", [(2, 3), (4, 5), (8, 2), (5, 4)])
+def test_cg_fixed_iterations_widths(sgp, orc, C, d):
+    """Channel counts that change how the tile kernels stage and split rows."""
+    _note(f"cg fixed iterations C={C} d={d}")
+    c = workloads.small_case(50 + C, 2500, d, channels=C, kind="mixture")
+    lat, olat = _build_both(sgp, orc, c.X, c.lengthscales)
+    x, iters, rel = sgp.cg_solve(lat, _cuda(c.values), 0.1, 0.0, max_iter=10)
+    xo, itero, relo, _ = olat.cg(c.values.astype(np.float64), 0.1, 0.0, max_iter=10)
+    assert np.all(iters == 10)
+    assert _colerr(x.cpu().numpy(), xo).max() <= CG_TOL
+
+
 def test_cg_to_tolerance(sgp, orc):
     _note("cg tolerance ws1")
     w = workloads.ws1()
@@ -318,3 +330,29 @@ def test_ws4_full_oracle(sgp, orc):
     _assert_structure(sgp, lat, olat)
     out = sgp.lattice_mvm(lat, _cuda(w.values)).cpu().numpy()
     assert _colerr(out, olat.mvm(w.values.astype(np.float64))).max() <= MVM_TOL
+
+
+@pytest.mark.parametrize("tol,max_iter", [(0.0, 45), (1e-6, 300)])
+def test_cg_graph_replay_matches_launches(sgp, tol, max_iter):
+    """CG with iteration blocks replayed from a graph equals the launch-by-
+    launch solve bitwise, over several solves with other work in between."""
+    _note(f"cg graph replay tol={tol} max_iter={max_iter}")
+    c = workloads.small_case(41, 6000, 6, channels=5, kind="mixture")
+    lat = sgp.lattice_build(_cuda(c.X), c.lengthscales)
+    B = _cuda(c.values)
+    prev = sgp.cg_graph_enable(False)
+    try:
+        x_ref, it_ref, rel_ref = sgp.cg_solve(lat, B, 0.05, tol, max_iter=max_iter)
+        x_ref = x_ref.cpu().numpy()
+        sgp.cg_graph_enable(True)
+        for rep in range(3):
+            sgp.lattice_mvm(lat, B)  # eager work between the graph solves
+            x, it, rel = sgp.cg_solve(lat, B, 0.05, tol, max_iter=max_iter)
+            np.testing.assert_array_equal(x.cpu().numpy(), x_ref)
+            np.testing.assert_array_equal(it, it_ref)
+            np.testing.assert_array_equal(rel, rel_ref)
+    finally:
+        sgp.cg_graph_enable(prev)
+        lat.free()
+    if tol > 0:
+        assert np.all(it_ref > 20)  # several replayed blocks ran
