@@ -13,6 +13,7 @@
 // (cond ~ 1e3..1e4) is already above a 1e-4 tolerance. The caller's rhs and
 // x are fp32. Partial sums are reduced in a fixed order, so a run is
 // reproducible given the MVM's own rounding.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -35,72 +36,99 @@ enum ScalarMode { SM_START = 0, SM_ALPHA = 1, SM_BETA = 2 };
 
 // Vectors live in the lattice's internal point order: b is gathered through
 // the permutation here and x scattered back in k_cg_out.
-template <int G>
+// The vector kernels give one partial sum per column for every chunk of
+// kCgChunk rows: 16 groups of 8 rows, each group added in row order, then the
+// 16 group sums in order. The order depends on the rows only, not on how
+// many columns are solved together, so a column's iterates are the same alone
+// or in a batch. A block takes kCpb(C) chunks at a time; thread (chunk,
+// group, column) has the column fastest, so the threads of a group read
+// whole rows.
+constexpr int kCgChunk = 128;
+constexpr int kCgGroups = 16;
+constexpr int kCgRowsPerGroup = kCgChunk / kCgGroups;
+__host__ __device__ inline int64_t cg_chunks(int64_t n) { return (n + kCgChunk - 1) / kCgChunk; }
+__host__ __device__ inline int cg_cpb(int C) {
+  const int per = kCgGroups * C;
+  return per >= kBlock ? 1 : kBlock / per;
+}
+
+// In LDS: the group sums of the block's chunks, [chunk][group][column].
+__device__ inline void cg_fold(double* sh, int64_t chunk0, int cpb, int64_t nchunks, int C,
+                               double* __restrict__ partials) {
+  __syncthreads();
+  for (int q = threadIdx.x; q < cpb * C; q += blockDim.x) {
+    const int ck = q / C, c = q - ck * C;
+    if (chunk0 + ck >= nchunks) continue;
+    double v = 0.0;
+    for (int g = 0; g < kCgGroups; ++g) v += sh[(ck * kCgGroups + g) * C + c];
+    partials[(chunk0 + ck) * C + c] = v;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
                                                     const uint32_t* __restrict__ perm,
                                                     double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p,
                                                     int64_t n, int C, int64_t rows,
                                                     double* __restrict__ partials) {
-  constexpr int R = kBlock / G;
-  const int lane = threadIdx.x % G;
-  const int64_t stride = (int64_t)gridDim.x * R;
-  double dot = 0.0;
-  if (lane < C) {
-    for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
-      const int64_t e = i * C + lane;
-      const int64_t src = perm[i];
-      const double v = (rows > 0 && src >= rows) ? 0.0 : (double)b[src * C + lane];
-      x[e] = 0.0;
-      r[e] = v;
-      p[e] = v;
-      dot += v * v;
+  __shared__ double sh[kCgGroups * kMaxCgCols];
+  const int cpb = cg_cpb(C);
+  const int64_t nchunks = cg_chunks(n);
+  for (int64_t chunk0 = (int64_t)blockIdx.x * cpb; chunk0 < nchunks; chunk0 += (int64_t)gridDim.x * cpb) {
+    for (int q = threadIdx.x; q < cpb * kCgGroups * C; q += blockDim.x) {
+      const int c = q % C, gq = q / C;  // gq = chunk * groups + group
+      const int64_t i0 = (chunk0 + gq / kCgGroups) * kCgChunk + (gq % kCgGroups) * kCgRowsPerGroup;
+      double dot = 0.0;
+      for (int64_t i = i0; i < i0 + kCgRowsPerGroup && i < n; ++i) {
+        const int64_t e = i * C + c;
+        const int64_t src = perm[i];
+        const double v = (rows > 0 && src >= rows) ? 0.0 : (double)b[src * C + c];
+        x[e] = 0.0;
+        r[e] = v;
+        p[e] = v;
+        dot += v * v;
+      }
+      sh[q] = dot;
     }
-  }
-  __shared__ double sh[kBlock];
-  sh[threadIdx.x] = dot;
-  __syncthreads();
-  if ((int)threadIdx.x < C) {
-    double s = 0.0;
-    for (int rr = 0; rr < R; ++rr) s += sh[rr * G + threadIdx.x];
-    partials[(int64_t)blockIdx.x * C + threadIdx.x] = s;
+    cg_fold(sh, chunk0, cpb, nchunks, C, partials);
   }
 }
 
 constexpr int kScalarThreads = 1024;
 
 // Sum the nparts partial rows of each column in a fixed order and apply one
-// step of the scalar recurrence. Thread (g, c) sums rows g, g + RG, ... of
-// column c (RG row groups, coalesced across c); one thread per column then
-// folds the RG group sums in order.
+// step of the scalar recurrence. Pair (g, c) sums rows g, g + kFold, ... of
+// column c; one thread per column then folds the kFold sums in order. The
+// order depends on nparts only, not on the number of columns.
+constexpr int kFold = 64;
 __global__ __launch_bounds__(kScalarThreads) void k_cg_scalar(const double* __restrict__ partials,
                                                               int64_t nparts, int C,
                                                               CgState* __restrict__ st, int mode,
                                                               double tol) {
-  __shared__ double sh[kScalarThreads];
+  __shared__ double sh[kFold * kMaxCgCols];
   const int tid = threadIdx.x;
-  const int RG = kScalarThreads / C;  // C <= 64, so RG >= 16
-  const int g = tid / C, c = tid - g * C;
-  double s = 0.0;
-  if (g < RG) {
+  for (int pair = tid; pair < kFold * C; pair += kScalarThreads) {
+    const int g = pair / C, c = pair - g * C;
+    double s = 0.0;
     int64_t b = g;
-    for (; b + 3 * RG < nparts; b += 4 * RG) {
+    for (; b + 3 * kFold < nparts; b += 4 * kFold) {
       const double a0 = partials[b * C + c];
-      const double a1 = partials[(b + RG) * C + c];
-      const double a2 = partials[(b + 2 * RG) * C + c];
-      const double a3 = partials[(b + 3 * RG) * C + c];
+      const double a1 = partials[(b + kFold) * C + c];
+      const double a2 = partials[(b + 2 * kFold) * C + c];
+      const double a3 = partials[(b + 3 * kFold) * C + c];
       s += a0;
       s += a1;
       s += a2;
       s += a3;
     }
-    for (; b < nparts; b += RG) s += partials[b * C + c];
+    for (; b < nparts; b += kFold) s += partials[b * C + c];
+    sh[pair] = s;
   }
-  sh[tid] = s;
   __syncthreads();
   if (tid < C) {
     double v = 0.0;
-    for (int gg = 0; gg < RG; ++gg) v += sh[gg * C + tid];
+    for (int gg = 0; gg < kFold; ++gg) v += sh[gg * C + tid];
     const int cc = tid;
     if (mode == SM_START) {
       st->rr[cc] = v;
@@ -136,33 +164,35 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_scalar(const double* __re
   }
 }
 
-template <int G>
+// x += alpha p, r -= alpha q, and the chunk partial sums of r.r.
 __global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
                                                       const double* __restrict__ p,
-                                                      const double* __restrict__ q, int64_t n, int C,
+                                                      const double* __restrict__ q_, int64_t n, int C,
                                                       const CgState* __restrict__ st,
                                                       double* __restrict__ partials) {
-  constexpr int R = kBlock / G;
-  const int lane = threadIdx.x % G;
-  const int64_t stride = (int64_t)gridDim.x * R;
-  double dot = 0.0;
-  if (lane < C) {
-    const double a = st->alpha[lane];
-    for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
-      const int64_t e = i * C + lane;
-      x[e] = __builtin_fma(a, p[e], x[e]);
-      const double rv = __builtin_fma(-a, q[e], r[e]);
-      r[e] = rv;
-      dot += rv * rv;
+  __shared__ double sh[kCgGroups * kMaxCgCols];
+  const int cpb = cg_cpb(C);
+  const int64_t nchunks = cg_chunks(n);
+  for (int64_t chunk0 = (int64_t)blockIdx.x * cpb; chunk0 < nchunks; chunk0 += (int64_t)gridDim.x * cpb) {
+    for (int q = threadIdx.x; q < cpb * kCgGroups * C; q += blockDim.x) {
+      const int c = q % C, gq = q / C;
+      const int64_t i0 = (chunk0 + gq / kCgGroups) * kCgChunk + (gq % kCgGroups) * kCgRowsPerGroup;
+      const double a = st->alpha[c];
+      double dot = 0.0;
+#pragma unroll
+      for (int k = 0; k < kCgRowsPerGroup; ++k) {
+        const int64_t i = i0 + k;
+        if (i < n) {
+          const int64_t e = i * C + c;
+          x[e] = __builtin_fma(a, p[e], x[e]);
+          const double rv = __builtin_fma(-a, q_[e], r[e]);
+          r[e] = rv;
+          dot += rv * rv;
+        }
+      }
+      sh[q] = dot;
     }
-  }
-  __shared__ double sh[kBlock];
-  sh[threadIdx.x] = dot;
-  __syncthreads();
-  if ((int)threadIdx.x < C) {
-    double s = 0.0;
-    for (int rr = 0; rr < R; ++rr) s += sh[rr * G + threadIdx.x];
-    partials[(int64_t)blockIdx.x * C + threadIdx.x] = s;
+    cg_fold(sh, chunk0, cpb, nchunks, C, partials);
   }
 }
 
@@ -198,8 +228,9 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   const int64_t n = L->n, nC = n * C;
   int rc;
   if ((rc = dev_reserve(L, Lm->cgvec, sizeof(double) * 4 * nC, s))) return rc;
-  // partial sums: kRedBlocks rows from the vector kernels, one row per tile from the slice
-  const int64_t nparts = L->ntiles > kRedBlocks ? L->ntiles : kRedBlocks;
+  // partial sums: one row per chunk from the vector kernels, one row per tile from the slice
+  const int64_t vparts = cg_chunks(n);
+  const int64_t nparts = L->ntiles > vparts ? L->ntiles : vparts;
   const size_t red_bytes = sizeof(double) * nparts * C + sizeof(CgState) + 256;
   if ((rc = dev_reserve(L, Lm->cgred, red_bytes, s))) return rc;
   double* x64 = (double*)Lm->cgvec.ptr;
@@ -215,16 +246,18 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     return SGP_ENOMEM;
   }
 
-  const dim3 grid(kRedBlocks), block(kBlock);
+  const dim3 block(kBlock);
+  const dim3 vgrid((unsigned)std::min<int64_t>((vparts + cg_cpb(C) - 1) / cg_cpb(C), 65536));
+  const dim3 grid(kRedBlocks);
   {
     ProfScope ps(KK_CG_INIT, s);
-    hipLaunchKernelGGL(k_cg_init<G>, grid, block, 0, s, b, (const uint32_t*)L->perm.ptr, x64, r, p, n, C,
+    hipLaunchKernelGGL(k_cg_init, vgrid, block, 0, s, b, (const uint32_t*)L->perm.ptr, x64, r, p, n, C,
                        L->solve_rows, partials);
     SGP_LAUNCH_CHECK("k_cg_init");
   }
   {
     ProfScope ps(KK_CG_SCALAR, s);
-    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, partials, (int64_t)kRedBlocks, C, st,
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, partials, vparts, C, st,
                        (int)SM_START, (double)tol);
     SGP_LAUNCH_CHECK("k_cg_scalar");
   }
@@ -242,12 +275,12 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     }
     {
       ProfScope ps(KK_CG_UPDATE, st_);
-      hipLaunchKernelGGL(k_cg_update<G>, grid, block, 0, st_, x64, r, p, q, n, C, st, partials);
+      hipLaunchKernelGGL(k_cg_update, vgrid, block, 0, st_, x64, r, p, q, n, C, st, partials);
       SGP_LAUNCH_CHECK("k_cg_update");
     }
     {
       ProfScope ps(KK_CG_SCALAR, st_);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, partials, (int64_t)kRedBlocks, C,
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, partials, vparts, C,
                          st, (int)SM_BETA, (double)tol);
       SGP_LAUNCH_CHECK("k_cg_scalar");
     }

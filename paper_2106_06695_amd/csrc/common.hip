@@ -290,9 +290,9 @@ int lattice_info(const sgp_lattice* L, int64_t* n, int32_t* d, int64_t* m, int64
   if (d) *d = L->d;
   if (m) *m = L->m;
   if (device_bytes)
-    *device_bytes = (int64_t)(L->perm.bytes + L->loc.bytes + L->ws.bytes + L->tile_off.bytes +
+    *device_bytes = (int64_t)(L->perm.bytes + L->loc.bytes + L->ws.bytes + L->tile_off.bytes + L->stile_off.bytes +
                               L->tile_verts.bytes + L->run_rel.bytes + L->ent_lp.bytes + L->ent_w.bytes +
-                              L->occ_ptr.bytes + L->run_dst.bytes + L->nbr.bytes + L->int2can.bytes +
+                              L->occ_ptr.bytes + L->run_dst.bytes + L->row_vert.bytes + L->nbr.bytes + L->int2can.bytes +
                               L->keys.bytes + L->ubuf.bytes + L->cgvec.bytes + L->cgred.bytes);
   return SGP_OK;
 }
@@ -353,8 +353,8 @@ void lattice_free(sgp_lattice* L) {
   if (!L) return;
   (void)hipSetDevice(L->device);
   (void)wait_last_use(L);
-  for (DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->tile_verts, &L->run_rel,
-                   &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->run_dst, &L->nbr, &L->int2can, &L->keys})
+  for (DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->stile_off, &L->tile_verts, &L->run_rel,
+                   &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->run_dst, &L->row_vert, &L->nbr, &L->int2can, &L->keys})
     dev_free(*b);
   dev_free(L->ubuf);
   dev_free(L->cgvec);

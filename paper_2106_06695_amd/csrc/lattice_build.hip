@@ -542,9 +542,9 @@ __global__ __launch_bounds__(kBlock) void k_run_flags(const unsigned long long* 
 
 // Run q of sorted entry p is (exclusive count of run starts before p) +
 // flag - 1. Entry p is the (p - tile * P * D)-th entry of its tile, since a
-// tile's entries are exactly those of its points. Writes the run lists (run
-// start relative to the tile, lattice point), the per-entry (point within
-// the tile, weight) in run order, and the tile offsets.
+// tile's entries are exactly those of its points. Writes each run's lattice
+// point, the per-entry (point within the tile, weight) in run order, and
+// the tile offsets.
 __global__ __launch_bounds__(kBlock) void k_run_fill(const unsigned long long* __restrict__ key,
                                                      const uint32_t* __restrict__ val,
                                                      const uint32_t* __restrict__ flag,
@@ -552,7 +552,6 @@ __global__ __launch_bounds__(kBlock) void k_run_fill(const unsigned long long* _
                                                      const sgp_entry* __restrict__ pm, int64_t L,
                                                      int D, int P, int mb, int64_t ntiles,
                                                      int32_t* __restrict__ tile_verts,
-                                                     uint16_t* __restrict__ run_rel,
                                                      uint8_t* __restrict__ ent_lp,
                                                      float* __restrict__ ent_w,
                                                      int32_t* __restrict__ tile_off) {
@@ -568,7 +567,6 @@ __global__ __launch_bounds__(kBlock) void k_run_fill(const unsigned long long* _
     ent_w[p] = pm[e].w;
     if (f) {
       tile_verts[q] = (int32_t)(k & jmask);
-      run_rel[q] = (uint16_t)(p - tile * (int64_t)P * D);
       if (p == 0 || (key[p - 1] >> mb) != (unsigned long long)tile) tile_off[tile] = (int32_t)q;
     }
     if (p == L - 1) tile_off[ntiles] = (int32_t)(q + 1);
@@ -593,26 +591,78 @@ __global__ __launch_bounds__(kBlock) void k_loc_fill(const unsigned long long* _
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_occ_keys(const int32_t* __restrict__ tile_verts, int64_t Q,
+// The splat reduces each run sequentially, so a run that many points of a
+// tile share would serialise the tile: runs are cut into pieces of at most
+// K entries, each reduced on its own and summed with the other partial rows
+// of its lattice point. First the start of every run ...
+__global__ __launch_bounds__(kBlock) void k_run_starts(const uint32_t* __restrict__ flag,
+                                                       const uint32_t* __restrict__ ex, int64_t L,
+                                                       uint32_t* __restrict__ start) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride)
+    if (flag[p]) start[ex[p]] = (uint32_t)p;
+}
+
+// ... then a piece starts where the offset within the run is a multiple of K
+// (flag rewritten in place, each entry by its own thread).
+__global__ __launch_bounds__(kBlock) void k_piece_flags(uint32_t* __restrict__ flag,
+                                                        const uint32_t* __restrict__ ex,
+                                                        const uint32_t* __restrict__ start, int64_t L,
+                                                        int K) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride) {
+    const uint32_t r = ex[p] + flag[p] - 1;
+    flag[p] = ((p - (int64_t)start[r]) % K == 0) ? 1u : 0u;
+  }
+}
+
+// Pieces: first entry relative to the tile, lattice point, first piece of
+// each tile.
+__global__ __launch_bounds__(kBlock) void k_piece_fill(const unsigned long long* __restrict__ key,
+                                                       const uint32_t* __restrict__ flag,
+                                                       const uint32_t* __restrict__ ex, int64_t L,
+                                                       int D, int P, int mb, int64_t ntiles,
+                                                       uint16_t* __restrict__ run_rel,
+                                                       int32_t* __restrict__ piece_vert,
+                                                       int32_t* __restrict__ stile_off) {
+  const unsigned long long jmask = (1ull << mb) - 1ull;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride) {
+    const unsigned long long k = key[p];
+    const uint32_t f = flag[p];
+    const int64_t q = (int64_t)ex[p] + f - 1;
+    const int64_t tile = (int64_t)(k >> mb);
+    if (f) {
+      piece_vert[q] = (int32_t)(k & jmask);
+      run_rel[q] = (uint16_t)(p - tile * (int64_t)P * D);
+      if (p == 0 || (key[p - 1] >> mb) != (unsigned long long)tile) stile_off[tile] = (int32_t)q;
+    }
+    if (p == L - 1) stile_off[ntiles] = (int32_t)(q + 1);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_occ_keys(const int32_t* __restrict__ vert, int64_t Q,
                                                      uint32_t* __restrict__ key,
                                                      uint32_t* __restrict__ val) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < Q; q += stride) {
-    key[q] = (uint32_t)tile_verts[q];
+    key[q] = (uint32_t)vert[q];
     val[q] = (uint32_t)q;
   }
 }
 
-// Runs sorted (stably) by lattice point: row o of the splat's partial buffer
-// belongs to run val[o]; each lattice point's rows are contiguous.
+// Pieces sorted (stably) by lattice point: row o of the splat's partial
+// buffer belongs to piece val[o]; each lattice point's rows are contiguous.
 __global__ __launch_bounds__(kBlock) void k_occ_fill(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ val, int64_t Q,
                                                      int64_t m, int32_t* __restrict__ occ_ptr,
-                                                     int32_t* __restrict__ run_dst) {
+                                                     int32_t* __restrict__ run_dst,
+                                                     int32_t* __restrict__ row_vert) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < Q; o += stride) {
     const uint32_t j = key[o];
     run_dst[val[o]] = (int32_t)o;
+    row_vert[o] = (int32_t)j;
     if (o == 0 || key[o - 1] != j) occ_ptr[j] = (int32_t)o;
     if (o == Q - 1) occ_ptr[m] = (int32_t)Q;
   }
@@ -626,7 +676,7 @@ unsigned grid_for(int64_t work, int64_t per_block, int64_t cap) {
 }
 
 struct Transient {
-  static constexpr int kSlots = 20;
+  static constexpr int kSlots = 24;
   void* ptr[kSlots] = {};
   hipStream_t s = nullptr;
   int alloc(int slot_i, size_t bytes) {
@@ -671,7 +721,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   int rc;
   enum {
     T_R0, T_RANK, T_SLOT, T_TAB, T_FIRST, T_COUNTS, T_OFFS, T_WORDS, T_IDX, T_W, T_NBRC,
-    T_SLOTS, T_FIRST2, T_CAN2INT, T_KA, T_KB, T_VA, T_VB, T_SORTTMP, T_PM
+    T_SLOTS, T_FIRST2, T_CAN2INT, T_KA, T_KB, T_VA, T_VB, T_SORTTMP, T_PM, T_SUB
   };
   if ((rc = tr.alloc(T_R0, sizeof(int32_t) * n * d))) return rc;
   if ((rc = tr.alloc(T_RANK, sizeof(uint8_t) * n * d))) return rc;
@@ -822,7 +872,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   uint32_t* vb = (uint32_t*)tr.ptr[T_VB];
   uint32_t* sort_tmp = (uint32_t*)tr.ptr[T_SORTTMP];
   for (sgp::DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->tile_verts, &L->run_rel,
-                         &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->run_dst, &L->nbr, &L->int2can})
+                         &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->run_dst, &L->row_vert, &L->stile_off, &L->nbr, &L->int2can})
     dev_free(*b);
   if ((rc = dev_alloc(L->perm, sizeof(uint32_t) * n, st))) return rc;
   // two spare slots: the slice reads slots in aligned pairs
@@ -924,50 +974,86 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     L->nrun = Q;
     if ((rc = dev_alloc(L->tile_off, sizeof(int32_t) * (ntiles + 1), st))) return rc;
     if ((rc = dev_alloc(L->tile_verts, sizeof(int32_t) * Q, st))) return rc;
-    if ((rc = dev_alloc(L->run_rel, sizeof(uint16_t) * Q, st))) return rc;
     // four spare bytes: the splat reads entry points four at a time
     if ((rc = dev_alloc(L->ent_lp, sizeof(uint8_t) * (Lel + 4), st))) return rc;
     if ((rc = dev_alloc(L->ent_w, sizeof(float) * Lel, st))) return rc;
-    if ((rc = dev_alloc(L->occ_ptr, sizeof(int32_t) * (m + 1), st))) return rc;
-    if ((rc = dev_alloc(L->run_dst, sizeof(int32_t) * Q, st))) return rc;
     {
       ProfScope ps(KK_ORDER, st);
       hipLaunchKernelGGL(k_run_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, sv,
                          flag, ex, (const sgp_entry*)tr.ptr[T_PM], Lel, D, P, mb, ntiles,
-                         (int32_t*)L->tile_verts.ptr, (uint16_t*)L->run_rel.ptr,
-                         (uint8_t*)L->ent_lp.ptr, (float*)L->ent_w.ptr, (int32_t*)L->tile_off.ptr);
+                         (int32_t*)L->tile_verts.ptr, (uint8_t*)L->ent_lp.ptr, (float*)L->ent_w.ptr,
+                         (int32_t*)L->tile_off.ptr);
       SGP_LAUNCH_CHECK("k_run_fill");
       hipLaunchKernelGGL(k_loc_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, sv,
                          flag, ex, (const int32_t*)L->tile_off.ptr, (const sgp_entry*)tr.ptr[T_PM],
                          Lel, mb, (uint16_t*)L->loc.ptr, (float*)L->ws.ptr);
       SGP_LAUNCH_CHECK("k_loc_fill");
     }
-    // runs grouped by lattice point (32-bit keys; reuses the sort buffers)
-    uint32_t* k32a = (uint32_t*)(in_alt ? kb : ka);
-    uint32_t* k32b = k32a + Q;
+    // the splat's pieces of at most kPiece entries per run
+    if ((rc = tr.alloc(T_SUB, sizeof(uint32_t) * Lel))) return rc;
+    uint32_t* sub = (uint32_t*)tr.ptr[T_SUB];
     {
       ProfScope ps(KK_ORDER, st);
-      hipLaunchKernelGGL(k_occ_keys, dim3(grid_for(Q, kBlock, 16384)), dim3(kBlock), 0, st,
-                         (const int32_t*)L->tile_verts.ptr, Q, k32a, va);
+      hipLaunchKernelGGL(k_run_starts, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, flag, ex,
+                         Lel, sub);
+      SGP_LAUNCH_CHECK("k_run_starts");
+      hipLaunchKernelGGL(k_piece_flags, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, flag, ex,
+                         (const uint32_t*)sub, Lel, kPiece);
+      SGP_LAUNCH_CHECK("k_piece_flags");
+    }
+    if ((rc = scan_exclusive_u32(flag, ex, Lel, words + 3, sort_tmp, st))) return rc;
+    SGP_HIP(hipMemcpyAsync(host_word + 3, words + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SGP_HIP(hipStreamSynchronize(st));
+    const int64_t Qs = host_word[3];
+    if (Qs < Q || Qs > Lel) {
+      set_error("lattice_build: inconsistent piece count %lld", (long long)Qs);
+      return SGP_EHASH;
+    }
+    L->npiece = Qs;
+    if ((rc = dev_alloc(L->stile_off, sizeof(int32_t) * (ntiles + 1), st))) return rc;
+    if ((rc = dev_alloc(L->run_rel, sizeof(uint16_t) * Qs, st))) return rc;
+    if ((rc = dev_alloc(L->occ_ptr, sizeof(int32_t) * (m + 1), st))) return rc;
+    if ((rc = dev_alloc(L->run_dst, sizeof(int32_t) * Qs, st))) return rc;
+    if ((rc = dev_alloc(L->row_vert, sizeof(int32_t) * Qs, st))) return rc;
+    {
+      ProfScope ps(KK_ORDER, st);
+      hipLaunchKernelGGL(k_piece_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, flag,
+                         ex, Lel, D, P, mb, ntiles, (uint16_t*)L->run_rel.ptr, (int32_t*)sub,
+                         (int32_t*)L->stile_off.ptr);
+      SGP_LAUNCH_CHECK("k_piece_fill");
+    }
+    // pieces grouped by lattice point (32-bit keys; reuses the sort buffers)
+    uint32_t* k32a = (uint32_t*)(in_alt ? kb : ka);
+    uint32_t* k32b = k32a + Qs;
+    {
+      ProfScope ps(KK_ORDER, st);
+      hipLaunchKernelGGL(k_occ_keys, dim3(grid_for(Qs, kBlock, 16384)), dim3(kBlock), 0, st,
+                         (const int32_t*)sub, Qs, k32a, va);
       SGP_LAUNCH_CHECK("k_occ_keys");
     }
     bool occ_alt = false;
-    if ((rc = radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, Q, mb, sort_tmp, st, &occ_alt))) return rc;
+    if ((rc = radix_sort_pairs<uint32_t>(k32a, va, k32b, vb, Qs, mb, sort_tmp, st, &occ_alt))) return rc;
     {
       ProfScope ps(KK_ORDER, st);
-      hipLaunchKernelGGL(k_occ_fill, dim3(grid_for(Q, kBlock, 16384)), dim3(kBlock), 0, st,
-                         occ_alt ? k32b : k32a, occ_alt ? vb : va, Q, m, (int32_t*)L->occ_ptr.ptr,
-                         (int32_t*)L->run_dst.ptr);
+      hipLaunchKernelGGL(k_occ_fill, dim3(grid_for(Qs, kBlock, 16384)), dim3(kBlock), 0, st,
+                         occ_alt ? k32b : k32a, occ_alt ? vb : va, Qs, m, (int32_t*)L->occ_ptr.ptr,
+                         (int32_t*)L->run_dst.ptr, (int32_t*)L->row_vert.ptr);
       SGP_LAUNCH_CHECK("k_occ_fill");
     }
-    // longest tile run list (sizes the slice's LDS stage)
-    std::vector<int32_t> toff(ntiles + 1);
+    // longest run list and piece list of a tile (size the LDS stages)
+    std::vector<int32_t> toff(ntiles + 1), soff(ntiles + 1);
     SGP_HIP(hipMemcpyAsync(toff.data(), L->tile_off.ptr, sizeof(int32_t) * (ntiles + 1),
                            hipMemcpyDeviceToHost, st));
+    SGP_HIP(hipMemcpyAsync(soff.data(), L->stile_off.ptr, sizeof(int32_t) * (ntiles + 1),
+                           hipMemcpyDeviceToHost, st));
     SGP_HIP(hipStreamSynchronize(st));
-    int mx = 0;
-    for (int64_t t = 0; t < ntiles; ++t) mx = std::max(mx, toff[t + 1] - toff[t]);
+    int mx = 0, ms = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      mx = std::max(mx, toff[t + 1] - toff[t]);
+      ms = std::max(ms, soff[t + 1] - soff[t]);
+    }
     L->max_tile_runs = mx;
+    L->max_tile_pieces = ms;
   }
   SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost, st));
   SGP_HIP(hipStreamSynchronize(st));

@@ -371,27 +371,67 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
   }
 }
 
-// Lattice point j sums its partial rows occ_ptr[j] .. occ_ptr[j+1]-1 (one
-// per tile touching it, contiguous); S = G*E lanes per point, E lanes
-// striding the rows, combined by a fixed butterfly.
+// U[j] = sum of lattice point j's partial rows occ_ptr[j] .. occ_ptr[j+1]-1
+// (one per piece of a run touching it, contiguous). The rows are cut into
+// ranges of kGatherRows; a group of G lanes adds its range's rows in order.
+// A lattice point whose rows lie in one range is written directly; the part
+// of a longer one that a range holds becomes a fragment (slot 0: it starts
+// the range; slot 1: it ends the range), summed in range order by
+// k_gather_fix. The work per group is fixed, whatever the list lengths.
+constexpr int kGatherRows = 64;
 template <typename TU, int G>
 __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restrict__ occ_ptr,
+                                                         const int32_t* __restrict__ row_vert,
                                                          const TU* __restrict__ part,
-                                                         TU* __restrict__ U, int64_t m, int C, int E,
-                                                         int64_t rows_per_block) {
-  const int S = G * E;
-  const int gl = threadIdx.x % S;
-  const int c0 = gl % G, u = gl / G;
-  const int groups = kBlock / S;
-  const int64_t j0 = xcd_block(blockIdx.x, gridDim.x) * rows_per_block;
-  const int64_t j1 = j0 + rows_per_block < m ? j0 + rows_per_block : m;
-  for (int64_t j = j0 + threadIdx.x / S; j < j1; j += groups) {
-    const int o0 = occ_ptr[j], o1 = occ_ptr[j + 1];
-    for (int c = c0; c < C; c += G) {
+                                                         TU* __restrict__ U, TU* __restrict__ frag,
+                                                         int64_t nrows, int C, int64_t ngroups) {
+  constexpr int GPB = kBlock / G;  // groups per block
+  const int lane = threadIdx.x % G;
+  const int64_t gi = xcd_block(blockIdx.x, gridDim.x) * GPB + threadIdx.x / G;
+  if (gi >= ngroups) return;
+  const int64_t o0 = gi * kGatherRows;
+  const int64_t o1 = o0 + kGatherRows < nrows ? o0 + kGatherRows : nrows;
+  for (int c = lane; c < C; c += G) {
+    int64_t o = o0;
+    while (o < o1) {
+      const int32_t j = row_vert[o];
+      const int64_t js = occ_ptr[j], je = occ_ptr[j + 1];
+      const int64_t e = je < o1 ? je : o1;
       TU acc = 0;
-      for (int o = o0 + u; o < o1; o += E) acc += part[(int64_t)o * C + c];
-      for (int off = G; off < S; off <<= 1) acc += __shfl_xor(acc, off);
-      if (u == 0) U[j * C + c] = acc;
+      for (int64_t k = o; k < e; ++k) acc += part[k * C + c];
+      if (js >= o0 && je <= o1)
+        U[(int64_t)j * C + c] = acc;
+      else
+        frag[(gi * 2 + (o == o0 ? 0 : 1)) * C + c] = acc;
+      o = e;
+    }
+  }
+}
+
+// Lattice points whose rows span several ranges: their fragments in order.
+__global__ __launch_bounds__(kBlock) void k_gather_fix(const int32_t* __restrict__ occ_ptr,
+                                                       const void* __restrict__ frag_v,
+                                                       void* __restrict__ U_v, int64_t m, int C,
+                                                       int elem) {
+  const int64_t total = m * C;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
+    const int64_t j = q / C;
+    const int c = (int)(q - j * C);
+    const int64_t js = occ_ptr[j], je = occ_ptr[j + 1];
+    const int64_t g0 = js / kGatherRows, g1 = (je - 1) / kGatherRows;
+    if (g0 == g1) continue;
+    const int64_t first = (g0 * 2 + (js == g0 * kGatherRows ? 0 : 1)) * C + c;
+    if (elem == 8) {
+      const double* frag = (const double*)frag_v;
+      double acc = frag[first];
+      for (int64_t g = g0 + 1; g <= g1; ++g) acc += frag[(g * 2) * C + c];
+      ((double*)U_v)[j * C + c] = acc;
+    } else {
+      const float* frag = (const float*)frag_v;
+      float acc = frag[first];
+      for (int64_t g = g0 + 1; g <= g1; ++g) acc += frag[(g * 2) * C + c];
+      ((float*)U_v)[j * C + c] = acc;
     }
   }
 }
@@ -463,7 +503,7 @@ __host__ __device__ inline SliceLds slice_lds(int P, int D, int maxq) {
   using S = TileShape<TU, G, kSliceBlock>;
   SliceLds o;
   size_t b = sizeof(TU) * (size_t)S::RC * S::RS;
-  const size_t red = sizeof(double) * kSliceBlock * S::VW;
+  const size_t red = sizeof(double) * (256 * 16 + 16 * 16);  // CG tile reduction
   if (b < red) b = red;
   o.w = b;
   b += sizeof(float) * (size_t)P * D;
@@ -662,12 +702,12 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
         }
       }
     }
-    double dot[S::VW];
-#pragma unroll
-    for (int i = 0; i < S::VW; ++i) dot[i] = 0.0;
+    double prod[S::PPG][S::VW];  // CG: p . out of each (point, channel)
 #pragma unroll
     for (int k = 0; k < S::PPG; ++k) {
       const int lp = grp + k * S::NG;
+#pragma unroll
+      for (int i = 0; i < S::VW; ++i) prod[k][i] = 0.0;
       if (lp < cur_np && live) {
         const int64_t pt = t * a.P + lp;
         TU o[S::VW];
@@ -677,7 +717,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
           o[i] = a.scale * acc[k][i];
           if (CG) {
             o[i] = masked ? (TU)0 : fma_t(a.noise, pv[k][i], o[i]);
-            dot[i] += (double)pv[k][i] * (double)o[i];
+            prod[k][i] = (double)pv[k][i] * (double)o[i];
           }
         }
         TU* dstp = out + (perm ? (int64_t)perm[pt] : pt) * a.C + cg;
@@ -691,27 +731,35 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
       }
     }
     if (CG) {
-      // per column: groups' sums in a fixed two-level order
-      __syncthreads();  // every lane is done with the staged rows
-      double* sh = (double*)smem;
+      // the tile's p . out per column: points in 16 blocks of 16, each block
+      // and then the blocks added in index order, so that the sum does not
+      // depend on how channels are split over lanes; 16 channels per pass
+      double* sh = (double*)smem;            // [256 points][16 channels]
+      double* sh2 = sh + 256 * 16;           // [16 blocks][16 channels]
+      for (int cs = 0; cs < G; cs += 16) {
+        __syncthreads();  // every lane is done with the staged rows / last pass
 #pragma unroll
-      for (int i = 0; i < S::VW; ++i) sh[tid * S::VW + i] = dot[i];
-      __syncthreads();
-      // thread (c, s): channel c of the chunk, groups s, s + 16, ...
-      constexpr int SPLIT = kSliceBlock / G < 16 ? kSliceBlock / G : 16;
-      double part2 = 0.0;
-      if (tid < G * SPLIT) {
-        const int c = tid % G, sidx = tid / G;
-        const int lane_in = c / S::VW, i = c % S::VW;
-        for (int g = sidx; g < S::NG; g += SPLIT) part2 += sh[(g * S::LPR + lane_in) * S::VW + i];
-      }
-      __syncthreads();
-      if (tid < G * SPLIT) sh[tid] = part2;
-      __syncthreads();
-      if (tid < G && ch * G + tid < a.C) {
-        double s = 0.0;
-        for (int sidx = 0; sidx < SPLIT; ++sidx) s += sh[sidx * G + tid];
-        partials[t * a.C + ch * G + tid] = s;
+        for (int k = 0; k < S::PPG; ++k) {
+          const int lp = grp + k * S::NG;
+#pragma unroll
+          for (int i = 0; i < S::VW; ++i) {
+            const int cc = cl + i - cs;
+            if (lp < 256 && cc >= 0 && cc < 16) sh[lp * 16 + cc] = prod[k][i];
+          }
+        }
+        __syncthreads();
+        if (tid < 256) {
+          const int c16 = tid % 16, blk = tid / 16;
+          double v = 0.0;
+          for (int q = blk * 16; q < blk * 16 + 16; ++q) v += q < cur_np ? sh[q * 16 + c16] : 0.0;
+          sh2[blk * 16 + c16] = v;
+        }
+        __syncthreads();
+        if (tid < 16 && cs + tid < G && ch * G + cs + tid < a.C) {
+          double v = 0.0;
+          for (int blk = 0; blk < 16; ++blk) v += sh2[blk * 16 + tid];
+          partials[t * a.C + ch * G + cs + tid] = v;
+        }
       }
     }
   }
@@ -767,6 +815,15 @@ unsigned persistent_grid(const void* kernel, int threads, size_t lds, int64_t it
   return (unsigned)g;
 }
 
+int64_t gather_ranges(const sgp_lattice* L) { return (L->npiece + kGatherRows - 1) / kGatherRows; }
+
+unsigned grid_cap(int64_t work) {
+  int64_t b = (work + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > 16384) b = 16384;
+  return (unsigned)b;
+}
+
 // Blocks for `rows` rows at R per block, capped, and the rows each block
 // takes so that the blocks cover all rows.
 void split_rows(int64_t rows, int R, int64_t cap, unsigned* blocks, int64_t* rows_per_block) {
@@ -787,6 +844,7 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   TU* B2 = B1 + mC;
   TU* B3 = B2 + mC;
   TU* part = B3 + mC;
+  TU* frag = part + L->npiece * C;  // 2 rows per gather range
   const int chunks = (C + G - 1) / G;
   const int P = L->tile_points;
   const dim3 tgrid((unsigned)L->ntiles, (unsigned)chunks);
@@ -802,26 +860,25 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
     sa.chunks = chunks;
     sa.vec_v = (TileShape<TU, G, kSplatBlock>::VEC && !perm && C == G && aligned16(V)) ? 1 : 0;
     sa.cvec = (C % Vec16<TU>::N == 0 && aligned16(part)) ? 1 : 0;
-    sa.lds = splat_lds<TU>(P, D, maxq, G);
+    sa.lds = splat_lds<TU>(P, D, L->max_tile_pieces, G);
     const unsigned grid = persistent_grid((const void*)&k_splat_tile<TU, G>, kSplatBlock, sa.lds.total, sa.items);
     hipLaunchKernelGGL((k_splat_tile<TU, G>), dim3(grid), dim3(kSplatBlock), sa.lds.total, s,
-                       (const int32_t*)L->tile_off.ptr, (const uint16_t*)L->run_rel.ptr,
+                       (const int32_t*)L->stile_off.ptr, (const uint16_t*)L->run_rel.ptr,
                        (const int32_t*)L->run_dst.ptr, (const uint8_t*)L->ent_lp.ptr,
                        (const float*)L->ent_w.ptr, V, perm, part, sa);
     SGP_LAUNCH_CHECK("k_splat_tile");
   }
   {
     ProfScope ps(KK_SPLAT_GATHER, s);
-    // lanes per point's list: about a quarter of its mean length
-    const double avg = (double)L->nrun / (double)m;
-    int E = 1;
-    while (E * 2 * G <= 64 && E * 2 <= avg / 4.0) E *= 2;
-    unsigned blocks;
-    int64_t rpb;
-    split_rows(m, kBlock / (G * E), 65536, &blocks, &rpb);
-    hipLaunchKernelGGL((k_splat_gather<TU, G>), dim3(blocks), dim3(kBlock), 0, s,
-                       (const int32_t*)L->occ_ptr.ptr, part, U0, m, C, E, rpb);
+    const int64_t ngroups = (L->npiece + kGatherRows - 1) / kGatherRows;
+    const int64_t blocks = (ngroups + kBlock / G - 1) / (kBlock / G);
+    hipLaunchKernelGGL((k_splat_gather<TU, G>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       (const int32_t*)L->occ_ptr.ptr, (const int32_t*)L->row_vert.ptr, part, U0, frag,
+                       L->npiece, C, ngroups);
     SGP_LAUNCH_CHECK("k_splat_gather");
+    hipLaunchKernelGGL(k_gather_fix, dim3(grid_cap(m * C)), dim3(kBlock), 0, s,
+                       (const int32_t*)L->occ_ptr.ptr, (const void*)frag, (void*)U0, m, C, (int)sizeof(TU));
+    SGP_LAUNCH_CHECK("k_gather_fix");
   }
 
   const bool sym = L->blur == SGP_BLUR_SYMMETRIC;
@@ -893,11 +950,11 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
 // tile kernels' LDS stages fit the budget.
 int chunk_lanes(const sgp_lattice* L, int C, size_t elem) {
   int g = lanes_for(C);
-  const int D = L->d + 1, P = L->tile_points, maxq = L->max_tile_runs;
+  const int D = L->d + 1, P = L->tile_points, maxq = L->max_tile_runs, maxp = L->max_tile_pieces;
   const size_t budget = (size_t)tuning().lds_budget;
   const size_t slice_budget = (size_t)tuning().slice_lds_budget;
   while (g > 1) {
-    const size_t splat = elem == 8 ? splat_lds<double>(P, D, maxq, g).total : splat_lds<float>(P, D, maxq, g).total;
+    const size_t splat = elem == 8 ? splat_lds<double>(P, D, maxp, g).total : splat_lds<float>(P, D, maxp, g).total;
     const size_t slice = elem == 8 ? slice_lds_g<double>(P, D, maxq, g) : slice_lds_g<float>(P, D, maxq, g);
     if (splat <= budget && slice <= slice_budget) break;
     g >>= 1;
@@ -909,7 +966,7 @@ template <typename TU>
 int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out,
                  hipStream_t s, TU noise, const TU* p, double* partials) {
   int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf,
-                       sizeof(TU) * (4 * L->m + L->nrun) * (size_t)C, s);
+                       sizeof(TU) * (4 * L->m + L->npiece + 2 * gather_ranges(L)) * (size_t)C, s);
   if (rc) return rc;
   switch (chunk_lanes(L, C, sizeof(TU))) {
     case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, partials);

@@ -16,6 +16,7 @@ constexpr int kMaxD = 32;       // largest input dimension
 constexpr int kMaxOrder = 8;    // largest stencil half-width r
 constexpr int kMaxCgCols = 64;  // columns per cg_solve call
 constexpr int kRedBlocks = 512; // blocks (and partial sums) of the reducing vector kernels
+constexpr int kPiece = 32;      // longest run piece the splat reduces in one go
 
 // Launch-shape knobs of the MVM kernels. Defaults are the measured best on
 // MI355X; SGP_LDS_BUDGET, SGP_SLICE_LDS_BUDGET and SGP_TILE_BLOCKS_PER_CU in
@@ -139,19 +140,23 @@ struct sgp_lattice {
   // splat reduces from LDS-staged values and the slice stages into LDS.
   int tile_points = 256;
   int64_t ntiles = 0;
-  int64_t nrun = 0;       // total runs over all tiles
-  int max_tile_runs = 0;  // longest tile vertex list
+  int64_t nrun = 0;         // total runs over all tiles
+  int max_tile_runs = 0;    // longest tile vertex list
+  int64_t npiece = 0;       // runs cut into pieces of at most kPiece entries (splat)
+  int max_tile_pieces = 0;  // longest tile piece list
   sgp::DevBuf perm;       // n uint32: sorted position -> caller's point index
   sgp::DevBuf loc;        // n(d+1) uint16: run of (sorted point, vertex) within its tile
   sgp::DevBuf ws;         // n(d+1) fp32: barycentric weight, sorted point order
   sgp::DevBuf tile_off;   // ntiles+1 int32: first run of each tile
   sgp::DevBuf tile_verts; // nrun int32: internal lattice point of each run (ascending per tile)
-  sgp::DevBuf run_rel;    // nrun uint16: first entry of each run, relative to its tile's entries
+  sgp::DevBuf stile_off;  // ntiles+1 int32: first piece of each tile
+  sgp::DevBuf run_rel;    // npiece uint16: first entry of each piece, relative to its tile's entries
   sgp::DevBuf ent_lp;     // n(d+1) uint8: point within its tile, entries grouped by run
   sgp::DevBuf ent_w;      // n(d+1) fp32: weight of each entry, grouped by run
   sgp::DevBuf occ_ptr;    // m+1 int32: first partial row of each lattice point
-  sgp::DevBuf run_dst;    // nrun int32: partial row of each run; a lattice point's runs
-                          //   occupy rows occ_ptr[j] .. occ_ptr[j+1]-1 in ascending run order
+  sgp::DevBuf row_vert;   // npiece int32: lattice point of each partial row
+  sgp::DevBuf run_dst;    // npiece int32: partial row of each piece; a lattice point's
+                          //   pieces occupy rows occ_ptr[j] .. occ_ptr[j+1]-1 in piece order
   sgp::DevBuf nbr;        // (d+1) x 2r x m int32: [direction][offset][internal vertex]
   sgp::DevBuf int2can;    // m int32: internal vertex -> canonical index
   sgp::DevBuf keys;       // m x d int32 in canonical order (first occurrence in caller's order)
@@ -159,7 +164,7 @@ struct sgp_lattice {
   hipEvent_t last_use = nullptr;  // recorded at the end of every call on the lattice
 
   // work buffers, grown on demand
-  sgp::DevBuf ubuf;   // lattice values 4 x m x C, then run partial sums nrun x C
+  sgp::DevBuf ubuf;   // lattice values 4 x m x C, piece partial sums npiece x C, gather fragments
   sgp::DevBuf cgvec;  // CG vectors x, r, p, q: 4 x n x C fp64
   sgp::DevBuf cgred;  // CG partial sums and per-column scalars
 };

@@ -5,7 +5,7 @@ one lattice MVM of [a; 0]), and the continuous-batching server.
 Bars: restricted CG with a fixed iteration count matches the oracle's
 restricted CG to a per-column relative error of 1e-4 (as the unrestricted CG
 parity test) and leaves the test rows exactly zero; the predictive mean from
-the GPU's a matches the oracle's MVM of the oracle's a to 1e-4; results of
+the GPU's a matches the oracle's MVM of that a to 1e-5 of |K| |a|; results of
 requests served together are bitwise equal to the same requests served one at
 a time; admission never reserves more than the HBM budget.
 """
@@ -19,6 +19,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 CG_TOL = 1e-4
+MVM_TOL = 1e-5
 
 
 def _note(msg):
@@ -45,6 +46,15 @@ def _colerr(got, ref):
     got = np.asarray(got, dtype=np.float64).reshape(ref.shape[0], -1)
     ref = ref.reshape(ref.shape[0], -1)
     return np.linalg.norm(got - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), 1e-300)
+
+
+def _assert_mean(olat, a, mu, n):
+    """The mean is a sum of kernel-weighted solution entries that can cancel,
+    so its error is bounded by the magnitude sum |K| |a| (the oracle's MVM of
+    |a|; the lattice weights are positive), not by the mean itself."""
+    ref = olat.mvm(a.astype(np.float64))[n:, 0]
+    scale = olat.mvm(np.abs(a).astype(np.float64))[n:, 0]
+    assert np.all(np.abs(mu - ref) <= MVM_TOL * scale + 1e-30)
 
 
 def _joint_case(seed, n, n_test, d, C):
@@ -74,14 +84,11 @@ def test_restricted_cg_and_predictive_mean(sgp, orc, seed, n, n_test, d, C, its)
     assert np.all(xg[n:] == 0.0)
     assert _colerr(xg[:n], xo[:n]).max() <= CG_TOL
     np.testing.assert_allclose(rel, relo, rtol=1e-3)
-    # predictive mean at the test rows: K(X*, X) a
+    # predictive mean at the test rows: K(X*, X) a, from the GPU's own a
     a = np.zeros((n + n_test, 1), dtype=np.float32)
     a[:n, 0] = xg[:n, 0]
     mu = sgp.lattice_mvm(lat, _cuda(a)).cpu().numpy()[n:, 0]
-    ao = np.zeros((n + n_test, 1))
-    ao[:n, 0] = xo[:n, 0]
-    muo = olat.mvm(ao)[n:, 0]
-    assert np.linalg.norm(mu - muo) <= CG_TOL * max(np.linalg.norm(muo), 1e-30)
+    _assert_mean(olat, a, mu, n)
     lat.free()
 
 
@@ -167,7 +174,6 @@ def test_server_request_matches_oracle(sgp, orc):
     xo, itero, _, _ = olat.cg(B, 0.1, 0.0, max_iter=15, rows=n)
     assert np.all(res.iters == 15)
     assert _colerr(res.alpha[:, None], xo[:n, :1]).max() <= CG_TOL
-    ao = np.zeros((1800, 1))
-    ao[:n, 0] = xo[:n, 0]
-    muo = olat.mvm(ao)[n:, 0]
-    assert np.linalg.norm(res.mean - muo) <= CG_TOL * np.linalg.norm(muo)
+    a = np.zeros((1800, 1), dtype=np.float32)
+    a[:n, 0] = res.alpha
+    _assert_mean(olat, a, res.mean, n)
