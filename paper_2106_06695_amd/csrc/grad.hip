@@ -155,11 +155,11 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
   const size_t sizes[4] = {sizeof(double) * n * CH, sizeof(double) * n * CH, sizeof(double) * n * d,
                            sizeof(double) * kColBlocks * d};
   for (int k = 0; k < 4; ++k) {
-    hipError_t e = hipMallocAsync(&bufs[k], sizes[k], s);
+    hipError_t e = pool_alloc(&bufs[k], sizes[k], s);
     if (e != hipSuccess) {
       bufs[k] = nullptr;
       (void)hipGetLastError();
-      set_error("lattice_mvm_grad: hipMallocAsync of %zu bytes failed", sizes[k]);
+      set_error("lattice_mvm_grad: device allocation of %zu bytes failed", sizes[k]);
       return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
     }
   }

@@ -675,23 +675,36 @@ unsigned grid_for(int64_t work, int64_t per_block, int64_t cap) {
   return (unsigned)b;
 }
 
+// Build temporaries. Once the stream has been synchronised after their last
+// use (idle), they go back to the block cache; otherwise they are released
+// in stream order.
 struct Transient {
   static constexpr int kSlots = 24;
   void* ptr[kSlots] = {};
+  size_t cap[kSlots] = {};
   hipStream_t s = nullptr;
+  bool idle = false;
   int alloc(int slot_i, size_t bytes) {
-    hipError_t e = hipMallocAsync(&ptr[slot_i], bytes ? bytes : 16, s);
+    if (!bytes) bytes = 16;
+    if ((ptr[slot_i] = block_take(bytes, &cap[slot_i]))) return SGP_OK;
+    cap[slot_i] = bytes;
+    hipError_t e = pool_alloc(&ptr[slot_i], bytes, s);
     if (e != hipSuccess) {
       ptr[slot_i] = nullptr;
       (void)hipGetLastError();
-      set_error("hipMallocAsync of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
       return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
     }
     return SGP_OK;
   }
   ~Transient() {
-    for (void* p : ptr)
-      if (p) (void)hipFreeAsync(p, s);
+    for (int i = 0; i < kSlots; ++i) {
+      if (!ptr[i]) continue;
+      if (idle)
+        block_give(ptr[i], cap[i]);
+      else
+        (void)hipFreeAsync(ptr[i], s);
+    }
   }
 };
 
@@ -1057,6 +1070,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   }
   SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost, st));
   SGP_HIP(hipStreamSynchronize(st));
+  tr.idle = true;  // every kernel of this attempt has finished
   if (host_word[0] & BF_COLLISION) *retry = true;
   if (!*retry && (int64_t)host_word[2] != m) {
     set_error("lattice_build: internal numbering found %u lattice points, expected %lld",
@@ -1164,6 +1178,8 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
     mark_use(L, st);
   }
   if (rc != SGP_OK) {
+    (void)hipStreamSynchronize(st);  // nothing may still use the buffers being released
+    (void)hipGetLastError();
     lattice_free(L);
     return rc;
   }

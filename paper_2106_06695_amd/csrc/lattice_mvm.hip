@@ -372,39 +372,64 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 }
 
 // U[j] = sum of lattice point j's partial rows occ_ptr[j] .. occ_ptr[j+1]-1
-// (one per piece of a run touching it, contiguous). The rows are cut into
-// ranges of kGatherRows; a group of G lanes adds its range's rows in order.
+// (one per piece of a run touching it, contiguous; row_vert names each row's
+// lattice point). The rows are cut into ranges of kGatherRows; a group of G
+// lanes adds its range's rows in order, eight rows loaded at a time.
 // A lattice point whose rows lie in one range is written directly; the part
 // of a longer one that a range holds becomes a fragment (slot 0: it starts
 // the range; slot 1: it ends the range), summed in range order by
 // k_gather_fix. The work per group is fixed, whatever the list lengths.
 constexpr int kGatherRows = 64;
 template <typename TU, int G>
-__global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restrict__ occ_ptr,
-                                                         const int32_t* __restrict__ row_vert,
+__global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restrict__ row_vert,
                                                          const TU* __restrict__ part,
                                                          TU* __restrict__ U, TU* __restrict__ frag,
                                                          int64_t nrows, int C, int64_t ngroups) {
   constexpr int GPB = kBlock / G;  // groups per block
+  constexpr int B = 8;             // rows loaded together
   const int lane = threadIdx.x % G;
   const int64_t gi = xcd_block(blockIdx.x, gridDim.x) * GPB + threadIdx.x / G;
   if (gi >= ngroups) return;
   const int64_t o0 = gi * kGatherRows;
   const int64_t o1 = o0 + kGatherRows < nrows ? o0 + kGatherRows : nrows;
+  // a segment is a whole lattice point unless it touches a range edge that
+  // its lattice point continues across
+  const int32_t before = o0 > 0 ? row_vert[o0 - 1] : -1;
+  const int32_t after = o1 < nrows ? row_vert[o1] : -1;
   for (int c = lane; c < C; c += G) {
-    int64_t o = o0;
-    while (o < o1) {
-      const int32_t j = row_vert[o];
-      const int64_t js = occ_ptr[j], je = occ_ptr[j + 1];
-      const int64_t e = je < o1 ? je : o1;
-      TU acc = 0;
-      for (int64_t k = o; k < e; ++k) acc += part[k * C + c];
-      if (js >= o0 && je <= o1)
-        U[(int64_t)j * C + c] = acc;
+    int32_t cur = row_vert[o0];
+    int64_t seg = o0;
+    TU acc = 0;
+    auto flush = [&](int64_t end) {
+      const bool whole = (seg > o0 || before != cur) && (end < o1 || after != cur);
+      if (whole)
+        U[(int64_t)cur * C + c] = acc;
       else
-        frag[(gi * 2 + (o == o0 ? 0 : 1)) * C + c] = acc;
-      o = e;
+        frag[(gi * 2 + (seg == o0 ? 0 : 1)) * C + c] = acc;
+    };
+    for (int64_t k0 = o0; k0 < o1; k0 += B) {
+      TU v[B];
+      int32_t rv[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int64_t k = k0 + u < o1 ? k0 + u : o1 - 1;
+        v[u] = part[k * C + c];
+        rv[u] = row_vert[k];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (k0 + u < o1) {
+          if (rv[u] != cur) {
+            flush(k0 + u);
+            cur = rv[u];
+            seg = k0 + u;
+            acc = 0;
+          }
+          acc += v[u];
+        }
+      }
     }
+    flush(o1);
   }
 }
 
@@ -873,8 +898,7 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
     const int64_t ngroups = (L->npiece + kGatherRows - 1) / kGatherRows;
     const int64_t blocks = (ngroups + kBlock / G - 1) / (kBlock / G);
     hipLaunchKernelGGL((k_splat_gather<TU, G>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                       (const int32_t*)L->occ_ptr.ptr, (const int32_t*)L->row_vert.ptr, part, U0, frag,
-                       L->npiece, C, ngroups);
+                       (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups);
     SGP_LAUNCH_CHECK("k_splat_gather");
     hipLaunchKernelGGL(k_gather_fix, dim3(grid_cap(m * C)), dim3(kBlock), 0, s,
                        (const int32_t*)L->occ_ptr.ptr, (const void*)frag, (void*)U0, m, C, (int)sizeof(TU));

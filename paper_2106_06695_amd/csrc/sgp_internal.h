@@ -88,7 +88,8 @@ class ProfScope {
 // Device buffer with byte accounting.
 struct DevBuf {
   void* ptr = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // requested
+  size_t cap = 0;    // allocated (a reused block may be larger)
 };
 
 // Device memory is stream-ordered: allocated on the stream of the call that
@@ -97,8 +98,15 @@ struct DevBuf {
 // the library synchronises the whole device, so lattices driven from
 // different streams overlap.
 int dev_alloc(DevBuf& b, size_t bytes, hipStream_t s);
+// Release a buffer the device is done with (the caller has waited for its
+// last use): it is kept for reuse by later allocations of a similar size.
 void dev_free(DevBuf& b);
+// The same for a raw block of cap bytes from pool_alloc.
+void block_give(void* p, size_t cap);
+void* block_take(size_t bytes, size_t* cap);
 hipStream_t lib_stream();
+// Stream-ordered allocation from the library's pool on the current device.
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
 // Pinned host scratch of at least `bytes` (<= 64 KiB), one per host thread.
 void* pinned_scratch(size_t bytes);
 
