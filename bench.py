@@ -59,6 +59,56 @@ def mvm_bytes(n, d, m, C, r, sym, cg=False):
             + kernel_bytes("slice", n, d, m, C, r, sym, cg))
 
 
+# Kernel sources whose code the stored HBM traffic was measured on; the
+# traffic is reported only while they are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ws3_traffic.json")
+TRAFFIC_SOURCES = ["paper_2106_06695_amd/csrc/lattice_mvm.hip", "paper_2106_06695_amd/csrc/sgp_internal.h",
+                   "paper_2106_06695_amd/csrc/cg.hip"]
+
+
+def sources_digest() -> dict:
+    import hashlib
+    return {f: hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() for f in TRAFFIC_SOURCES}
+
+
+def stored_traffic(stage: str):
+    """HBM bytes per launch of a stage from the committed FETCH_SIZE /
+    WRITE_SIZE measurement (copy-calibrated), or None if the kernel sources
+    changed since."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != sources_digest():
+        return None
+    k = t.get("stages", {}).get(stage)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
+def probe():
+    """A few CG iterations of the ws3 step (every MVM and CG kernel), then a
+    plain 512 MiB device copy whose FETCH_SIZE / WRITE_SIZE calibrate the
+    counters."""
+    import torch
+    import paper_2106_06695_amd as sgp
+    import workloads
+    torch.cuda.set_device(0)
+    w = workloads.ws3()
+    X = torch.from_numpy(w.X).cuda()
+    V = torch.from_numpy(w.values).cuda()
+    lat = sgp.lattice_build(X, w.lengthscales)
+    x = torch.empty_like(V)
+    sgp.cg_solve(lat, V, w.noise, 0.0, max_iter=3, x=x)
+    a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    lat.free()
+    print(json.dumps({"probe": "ws3 build + 3 CG iterations, then a 512 MiB device copy", "m": lat.m}),
+          flush=True)
+    return 0
+
+
 def cpu_baseline(w, n_sample: int, iters: int):
     """The oracle as it stands: build + per-column CG on the first n_sample
     points, single-threaded."""
@@ -121,10 +171,14 @@ def main(argv=None):
     ap.add_argument("--serve", type=int, default=0,
                     help="also run the serving benchmark with this many requests (0 = skip)")
     ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--probe", action="store_true",
+                    help="only run the short counter-collection workload")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         return 2
+    if args.probe:
+        return probe()
 
     import torch
     import paper_2106_06695_amd as sgp
@@ -228,7 +282,7 @@ def main(argv=None):
                    "cg_iterations": iters, "blur": args.blur},
         "roofline": {"bound": "hbm", "kernel": dom + (" (splat_tile + splat_gather)" if dom == "splat" else ""),
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom),
                      "algo_bytes_per_launch": dom_bytes},
         "mvm_only": {"ms": mvm_s * 1e3, "points_ch_per_s": n * C / mvm_s,
                      "algo_bytes": B, "algo_GBps": B / mvm_s / 1e9,
