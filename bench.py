@@ -41,10 +41,10 @@ def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, c
         return n * D * 8 + chains * m * C * ub + n * C * vb + (n * C * vb if cg else 0)
     if kind == "blur":       # per chain: U in, U out, neighbour lists
         return chains * (2 * m * C * ub + T * m * 4)
-    if kind == "cg_update":  # x, p, q, r in; x, r out (fp64)
-        return 6 * n * C * 8
-    if kind == "cg_dir":     # r, p in; p out (fp64)
+    if kind == "cg_update":  # q, r in; r out (fp64)
         return 3 * n * C * 8
+    if kind == "cg_dir":     # x, p, r in; x, p out (fp64)
+        return 5 * n * C * 8
     if kind == "cg_init":    # b in (fp32); x, r, p out (fp64)
         return n * C * 4 + 3 * n * C * 8
     if kind == "cg_out":     # x in (fp64), x out (fp32)

@@ -164,9 +164,9 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_scalar(const double* __re
   }
 }
 
-// x += alpha p, r -= alpha q, and the chunk partial sums of r.r.
-__global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
-                                                      const double* __restrict__ p,
+// r -= alpha q, and the chunk partial sums of r.r (x moves in k_cg_dir,
+// which reads p anyway).
+__global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ r,
                                                       const double* __restrict__ q_, int64_t n, int C,
                                                       const CgState* __restrict__ st,
                                                       double* __restrict__ partials) {
@@ -184,7 +184,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ x, do
         const int64_t i = i0 + k;
         if (i < n) {
           const int64_t e = i * C + c;
-          x[e] = __builtin_fma(a, p[e], x[e]);
           const double rv = __builtin_fma(-a, q_[e], r[e]);
           r[e] = rv;
           dot += rv * rv;
@@ -196,17 +195,38 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ x, do
   }
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_cg_dir(const double* __restrict__ r, double* __restrict__ p,
-                                                   int64_t n, int C, const CgState* __restrict__ st) {
-  constexpr int R = kBlock / G;
-  const int lane = threadIdx.x % G;
-  if (lane >= C || !st->active[lane]) return;
-  const double beta = st->beta[lane];
-  const int64_t stride = (int64_t)gridDim.x * R;
-  for (int64_t i = (int64_t)blockIdx.x * R + threadIdx.x / G; i < n; i += stride) {
-    const int64_t e = i * C + lane;
-    p[e] = __builtin_fma(beta, p[e], r[e]);
+// x += alpha p with this iteration's alpha (zero for a column that was
+// already converged), then p = r + beta p for the columns still active.
+// Element-wise over the n x C arrays, two elements (one 16-byte access) per
+// step when C is even.
+__global__ __launch_bounds__(kBlock) void k_cg_dir(double* __restrict__ x, const double* __restrict__ r,
+                                                   double* __restrict__ p, int64_t nC, int C,
+                                                   const CgState* __restrict__ st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((C & 1) == 0) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2* x2 = (d2*)x;
+    d2* p2 = (d2*)p;
+    const d2* r2 = (const d2*)r;
+    for (int64_t h = t0; h < nC / 2; h += stride) {
+      const int c = (int)((2 * h) % C);
+      const d2 pv = p2[h], xv = x2[h], rv = r2[h];
+      d2 xo, po;
+      xo[0] = __builtin_fma(st->alpha[c], pv[0], xv[0]);
+      xo[1] = __builtin_fma(st->alpha[c + 1], pv[1], xv[1]);
+      po[0] = st->active[c] ? __builtin_fma(st->beta[c], pv[0], rv[0]) : pv[0];
+      po[1] = st->active[c + 1] ? __builtin_fma(st->beta[c + 1], pv[1], rv[1]) : pv[1];
+      x2[h] = xo;
+      p2[h] = po;
+    }
+  } else {
+    for (int64_t e = t0; e < nC; e += stride) {
+      const int c = (int)(e % C);
+      const double pv = p[e];
+      x[e] = __builtin_fma(st->alpha[c], pv, x[e]);
+      if (st->active[c]) p[e] = __builtin_fma(st->beta[c], pv, r[e]);
+    }
   }
 }
 
@@ -249,6 +269,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   const dim3 block(kBlock);
   const dim3 vgrid((unsigned)std::min<int64_t>((vparts + cg_cpb(C) - 1) / cg_cpb(C), 65536));
   const dim3 grid(kRedBlocks);
+  const dim3 dgrid((unsigned)std::min<int64_t>((nC / 2 + kBlock - 1) / kBlock + 1, 65536));
   {
     ProfScope ps(KK_CG_INIT, s);
     hipLaunchKernelGGL(k_cg_init, vgrid, block, 0, s, b, (const uint32_t*)L->perm.ptr, x64, r, p, n, C,
@@ -275,7 +296,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     }
     {
       ProfScope ps(KK_CG_UPDATE, st_);
-      hipLaunchKernelGGL(k_cg_update, vgrid, block, 0, st_, x64, r, p, q, n, C, st, partials);
+      hipLaunchKernelGGL(k_cg_update, vgrid, block, 0, st_, r, q, n, C, st, partials);
       SGP_LAUNCH_CHECK("k_cg_update");
     }
     {
@@ -286,7 +307,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     }
     {
       ProfScope ps(KK_CG_DIR, st_);
-      hipLaunchKernelGGL(k_cg_dir<G>, grid, block, 0, st_, r, p, n, C, st);
+      hipLaunchKernelGGL(k_cg_dir, dgrid, block, 0, st_, x64, r, p, nC, C, st);
       SGP_LAUNCH_CHECK("k_cg_dir");
     }
     return SGP_OK;

@@ -471,48 +471,84 @@ struct BlurArgs {
   int r;
   int chains;
   int sum_out;  // last SYMMETRIC step: out[0] = forward + reverse
+  int vec;      // rows of C channels start 16-byte aligned
   int64_t rows_per_block;
   TU st[2 * kMaxOrder + 1];
 };
 
-template <typename TU>
-__device__ __forceinline__ TU blur_row(const TU* __restrict__ in, const int32_t* __restrict__ nb,
-                                       int64_t m, int64_t j, int C, int c, int r, const TU* st) {
-  TU acc = 0;
+// One chain's blur of VW channels of row j: sum over t = -r..r of
+// stencil[t] * U[neighbour(j, t)], in t order; a missing neighbour adds 0.
+template <typename TU, int VW>
+__device__ __forceinline__ void blur_rows(const TU* __restrict__ in, const int32_t* __restrict__ nb,
+                                          int64_t m, int64_t j, int C, int c, int r, const TU* st,
+                                          bool vec, TU (&acc)[VW]) {
+#pragma unroll
+  for (int i = 0; i < VW; ++i) acc[i] = 0;
+  // neighbour rows first (2r independent loads), then the values
+  int32_t nbv[2 * kMaxOrder];
+  for (int ti = 0; ti < 2 * r; ++ti) nbv[ti] = nb[(int64_t)ti * m + j];
   int ti = 0;
   for (int t = -r; t <= r; ++t) {
-    TU v;
-    if (t == 0) {
-      v = in[j * C + c];
+    const int64_t row = t == 0 ? j : (int64_t)nbv[ti++];
+    TU v[VW];
+    if (row >= 0) {
+      const TU* src = in + row * C + c;
+      if (vec) {
+        read_row<TU, VW>(src, v);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VW; ++i) v[i] = c + i < C ? src[i] : (TU)0;
+      }
     } else {
-      const int32_t x = nb[(int64_t)ti * m + j];
-      v = x >= 0 ? in[(int64_t)x * C + c] : (TU)0;
-      ++ti;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) v[i] = 0;
     }
-    acc = fma_t(st[t + r], v, acc);
+#pragma unroll
+    for (int i = 0; i < VW; ++i) acc[i] = fma_t(st[t + r], v[i], acc[i]);
   }
-  return acc;
 }
 
+template <int G>
+__host__ __device__ constexpr int blur_vw() { return G < 4 ? G : 4; }
+
+// One thread per (row, VW channels).
 template <typename TU, int G>
 __global__ __launch_bounds__(kBlock) void k_blur(BlurArgs<TU> a) {
-  constexpr int R = kBlock / G;
-  const int lane = threadIdx.x % G;
+  constexpr int VW = blur_vw<G>();
+  constexpr int LPR = G / VW;
+  constexpr int R = kBlock / LPR;
+  const int sub = threadIdx.x % LPR;
   const int64_t j0 = xcd_block(blockIdx.x, gridDim.x) * a.rows_per_block;
   const int64_t j1 = j0 + a.rows_per_block < a.m ? j0 + a.rows_per_block : a.m;
-  for (int64_t j = j0 + threadIdx.x / G; j < j1; j += R) {
-    for (int c = lane; c < a.C; c += G) {
-      const TU f = blur_row(a.in[0], a.nbr[0], a.m, j, a.C, c, a.r, a.st);
+  for (int64_t j = j0 + threadIdx.x / LPR; j < j1; j += R) {
+    for (int c = sub * VW; c < a.C; c += G) {
+      const bool vec = a.vec && c + VW <= a.C;
+      TU f[VW];
+      blur_rows<TU, VW>(a.in[0], a.nbr[0], a.m, j, a.C, c, a.r, a.st, vec, f);
       if (a.chains == 2) {
-        const TU b = blur_row(a.in[1], a.nbr[1], a.m, j, a.C, c, a.r, a.st);
+        TU b[VW];
+        blur_rows<TU, VW>(a.in[1], a.nbr[1], a.m, j, a.C, c, a.r, a.st, vec, b);
         if (a.sum_out) {
-          a.out[0][j * a.C + c] = f + b;
+#pragma unroll
+          for (int i = 0; i < VW; ++i) f[i] = f[i] + b[i];
         } else {
-          a.out[0][j * a.C + c] = f;
-          a.out[1][j * a.C + c] = b;
+          TU* o1 = a.out[1] + j * a.C + c;
+          if (vec) {
+            write_row<TU, VW>(o1, b);
+          } else {
+#pragma unroll
+            for (int i = 0; i < VW; ++i)
+              if (c + i < a.C) o1[i] = b[i];
+          }
         }
+      }
+      TU* o0 = a.out[0] + j * a.C + c;
+      if (vec) {
+        write_row<TU, VW>(o0, f);
       } else {
-        a.out[0][j * a.C + c] = f;
+#pragma unroll
+        for (int i = 0; i < VW; ++i)
+          if (c + i < a.C) o0[i] = f[i];
       }
     }
   }
@@ -913,7 +949,8 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   a.chains = sym ? 2 : 1;
   for (int t = 0; t < 2 * L->order + 1; ++t) a.st[t] = (TU)L->stencil64[t];
   unsigned bblocks;
-  split_rows(m, kBlock / G, 65536, &bblocks, &a.rows_per_block);
+  split_rows(m, kBlock / (G / blur_vw<G>()), 65536, &bblocks, &a.rows_per_block);
+  a.vec = (C % Vec16<TU>::N == 0 && blur_vw<G>() % Vec16<TU>::N == 0 && aligned16(U0)) ? 1 : 0;
   const int32_t* nbr = (const int32_t*)L->nbr.ptr;
   const TU* cur[2] = {U0, U0};
   for (int step = 0; step <= d; ++step) {
