@@ -1,10 +1,11 @@
 // Conjugate gradients on (outputscale*K + noise*I) x = b, one independent
 // recurrence per column (Section 2, Krylov methods; Section 5.4 on
 // tolerances). All scalars stay on the device: the slice of each MVM emits
-// per-block partial sums of p.q, a one-block kernel turns them into alpha,
-// the update kernel moves x and r and emits partial sums of r.r, and a
-// second one-block kernel decides convergence and beta. The host only polls
-// the per-column "active" flags every few iterations.
+// per-tile partial sums of p.q and its last block to finish turns them into
+// alpha; the update kernel moves r and emits partial sums of r.r, from which a
+// one-block kernel decides convergence and beta; the direction kernel moves x
+// and p. The
+// host only polls the per-column "active" flags every few iterations.
 //
 // Precision: the solver's vectors (x, r, p, q), the lattice values inside
 // its MVMs and all reductions are fp64; only the barycentric weights stay
@@ -17,182 +18,139 @@
 #include <cmath>
 #include <cstring>
 
+#include "cg_step.h"
 #include "sgp_internal.h"
 
 namespace sgp {
 namespace {
 
-struct CgState {
-  double rr[kMaxCgCols];
-  double bnorm[kMaxCgCols];
-  double alpha[kMaxCgCols];
-  double beta[kMaxCgCols];
-  float rel[kMaxCgCols];
-  int32_t active[kMaxCgCols];
-  int32_t iters[kMaxCgCols];
-};
-
-enum ScalarMode { SM_START = 0, SM_ALPHA = 1, SM_BETA = 2 };
-
 // Vectors live in the lattice's internal point order: b is gathered through
 // the permutation here and x scattered back in k_cg_out.
-// The vector kernels give one partial sum per column for every chunk of
-// kCgChunk rows: 16 groups of 8 rows, each group added in row order, then the
-// 16 group sums in order. The order depends on the rows only, not on how
-// many columns are solved together, so a column's iterates are the same alone
-// or in a batch. A block takes kCpb(C) chunks at a time; thread (chunk,
-// group, column) has the column fastest, so the threads of a group read
-// whole rows.
+// The vector kernels give one partial sum per column for every superchunk of
+// S chunks of kCgChunk rows. A chunk is 16 groups of 8 rows, each group added
+// in row order, then the 16 group sums in order; a superchunk adds its chunk
+// sums in order. The order depends on the rows only, not on how many columns
+// are solved together, so a column's iterates are the same alone or in a
+// batch. A block takes a superchunk at a time, kCpb(C) chunks per pass;
+// thread (chunk, group, column) has the column fastest, so the threads of a
+// group read whole rows. The update kernel, once per iteration, uses S = 16
+// (2048 rows), which keeps the scalar step's fold short; the init kernel
+// uses S = 1, which gives it more blocks for its gathered loads.
 constexpr int kCgChunk = 128;
 constexpr int kCgGroups = 16;
 constexpr int kCgRowsPerGroup = kCgChunk / kCgGroups;
+constexpr int kSuperUpdate = 16;
+constexpr int kSuperInit = 1;
 __host__ __device__ inline int64_t cg_chunks(int64_t n) { return (n + kCgChunk - 1) / kCgChunk; }
+__host__ __device__ inline int64_t cg_supers(int64_t n, int S) { return (cg_chunks(n) + S - 1) / S; }
 __host__ __device__ inline int cg_cpb(int C) {
   const int per = kCgGroups * C;
   return per >= kBlock ? 1 : kBlock / per;
 }
+// Dynamic LDS of a vector kernel: the group sums of one pass.
+inline size_t cg_vec_lds(int C) { return sizeof(double) * (size_t)(cg_cpb(C) * kCgGroups * C); }
 
-// In LDS: the group sums of the block's chunks, [chunk][group][column].
-__device__ inline void cg_fold(double* sh, int64_t chunk0, int cpb, int64_t nchunks, int C,
-                               double* __restrict__ partials) {
-  __syncthreads();
-  for (int q = threadIdx.x; q < cpb * C; q += blockDim.x) {
-    const int ck = q / C, c = q - ck * C;
-    if (chunk0 + ck >= nchunks) continue;
-    double v = 0.0;
-    for (int g = 0; g < kCgGroups; ++g) v += sh[(ck * kCgGroups + g) * C + c];
-    partials[(chunk0 + ck) * C + c] = v;
+// Runs gsum(first row, column) for every group of the block's superchunks
+// and writes one partial per superchunk and column.
+template <int S, typename GroupSum>
+__device__ inline void cg_partials(int64_t n, int C, double* __restrict__ partials, double* sh,
+                                   GroupSum gsum) {
+  const int cpb = cg_cpb(C);
+  const int64_t nchunks = cg_chunks(n), nsup = cg_supers(n, S);
+  for (int64_t sup = blockIdx.x; sup < nsup; sup += gridDim.x) {
+    const int64_t c0 = sup * S;
+    const int64_t c1 = c0 + S < nchunks ? c0 + S : nchunks;
+    double acc = 0.0;  // thread c < C: column c's superchunk sum so far
+    for (int64_t chunk0 = c0; chunk0 < c1; chunk0 += cpb) {
+      const int nck = (int)(c1 - chunk0 < cpb ? c1 - chunk0 : cpb);
+      for (int q = threadIdx.x; q < nck * kCgGroups * C; q += blockDim.x) {
+        const int c = q % C, gq = q / C;  // gq = chunk * groups + group
+        sh[q] = gsum((chunk0 + gq / kCgGroups) * kCgChunk + (gq % kCgGroups) * kCgRowsPerGroup, c);
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < C) {
+        for (int ck = 0; ck < nck; ++ck) {
+          double v = 0.0;
+          for (int g = 0; g < kCgGroups; ++g) v += sh[(ck * kCgGroups + g) * C + threadIdx.x];
+          acc += v;
+        }
+      }
+      __syncthreads();
+    }
+    if ((int)threadIdx.x < C) partials[sup * C + threadIdx.x] = acc;
   }
-  __syncthreads();
 }
 
+// x = 0, r = p = b (rows at or past `rows` zero when rows > 0), and the
+// starting r.r.
 __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
                                                     const uint32_t* __restrict__ perm,
                                                     double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p,
                                                     int64_t n, int C, int64_t rows,
                                                     double* __restrict__ partials) {
-  __shared__ double sh[kCgGroups * kMaxCgCols];
-  const int cpb = cg_cpb(C);
-  const int64_t nchunks = cg_chunks(n);
-  for (int64_t chunk0 = (int64_t)blockIdx.x * cpb; chunk0 < nchunks; chunk0 += (int64_t)gridDim.x * cpb) {
-    for (int q = threadIdx.x; q < cpb * kCgGroups * C; q += blockDim.x) {
-      const int c = q % C, gq = q / C;  // gq = chunk * groups + group
-      const int64_t i0 = (chunk0 + gq / kCgGroups) * kCgChunk + (gq % kCgGroups) * kCgRowsPerGroup;
-      double dot = 0.0;
-      for (int64_t i = i0; i < i0 + kCgRowsPerGroup && i < n; ++i) {
-        const int64_t e = i * C + c;
-        const int64_t src = perm[i];
-        const double v = (rows > 0 && src >= rows) ? 0.0 : (double)b[src * C + c];
+  extern __shared__ double dsh[];
+  cg_partials<kSuperInit>(n, C, partials, dsh, [=](int64_t i0, int c) {
+    // all loads of the group first, then the stores
+    uint32_t src[kCgRowsPerGroup];
+    double v[kCgRowsPerGroup];
+#pragma unroll
+    for (int k = 0; k < kCgRowsPerGroup; ++k) src[k] = i0 + k < n ? perm[i0 + k] : 0u;
+#pragma unroll
+    for (int k = 0; k < kCgRowsPerGroup; ++k)
+      v[k] = (i0 + k < n && !(rows > 0 && src[k] >= rows)) ? (double)b[(int64_t)src[k] * C + c] : 0.0;
+    double dot = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCgRowsPerGroup; ++k) {
+      if (i0 + k < n) {
+        const int64_t e = (i0 + k) * C + c;
         x[e] = 0.0;
-        r[e] = v;
-        p[e] = v;
-        dot += v * v;
+        r[e] = v[k];
+        p[e] = v[k];
+        dot += v[k] * v[k];
       }
-      sh[q] = dot;
     }
-    cg_fold(sh, chunk0, cpb, nchunks, C, partials);
-  }
+    return dot;
+  });
 }
 
-constexpr int kScalarThreads = 1024;
-
-// Sum the nparts partial rows of each column in a fixed order and apply one
-// step of the scalar recurrence. Pair (g, c) sums rows g, g + kFold, ... of
-// column c; one thread per column then folds the kFold sums in order. The
-// order depends on nparts only, not on the number of columns.
-constexpr int kFold = 64;
-__global__ __launch_bounds__(kScalarThreads) void k_cg_scalar(const double* __restrict__ partials,
-                                                              int64_t nparts, int C,
-                                                              CgState* __restrict__ st, int mode,
-                                                              double tol) {
-  __shared__ double sh[kFold * kMaxCgCols];
-  const int tid = threadIdx.x;
-  for (int pair = tid; pair < kFold * C; pair += kScalarThreads) {
-    const int g = pair / C, c = pair - g * C;
-    double s = 0.0;
-    int64_t b = g;
-    for (; b + 3 * kFold < nparts; b += 4 * kFold) {
-      const double a0 = partials[b * C + c];
-      const double a1 = partials[(b + kFold) * C + c];
-      const double a2 = partials[(b + 2 * kFold) * C + c];
-      const double a3 = partials[(b + 3 * kFold) * C + c];
-      s += a0;
-      s += a1;
-      s += a2;
-      s += a3;
-    }
-    for (; b < nparts; b += kFold) s += partials[b * C + c];
-    sh[pair] = s;
-  }
-  __syncthreads();
-  if (tid < C) {
-    double v = 0.0;
-    for (int gg = 0; gg < kFold; ++gg) v += sh[gg * C + tid];
-    const int cc = tid;
-    if (mode == SM_START) {
-      st->rr[cc] = v;
-      st->bnorm[cc] = sqrt(v);
-      st->active[cc] = v > 0.0 ? 1 : 0;
-      st->iters[cc] = 0;
-      st->rel[cc] = v > 0.0 ? 1.f : 0.f;
-      st->alpha[cc] = 0.0;
-      st->beta[cc] = 0.0;
-    } else if (mode == SM_ALPHA) {
-      if (st->active[cc] && v > 0.0) {
-        st->alpha[cc] = st->rr[cc] / v;
-      } else {
-        st->alpha[cc] = 0.0;
-        st->active[cc] = 0;  // converged, or breakdown (p.Ap <= 0)
-      }
-    } else {
-      if (st->active[cc]) {
-        st->iters[cc] += 1;
-        const double rel = sqrt(v) / st->bnorm[cc];
-        st->rel[cc] = (float)rel;
-        if (rel <= tol) {
-          st->active[cc] = 0;
-          st->beta[cc] = 0.0;
-        } else {
-          st->beta[cc] = v / st->rr[cc];
-          st->rr[cc] = v;
-        }
-      } else {
-        st->beta[cc] = 0.0;
-      }
-    }
-  }
-}
-
-// r -= alpha q, and the chunk partial sums of r.r (x moves in k_cg_dir,
-// which reads p anyway).
+// r -= alpha q, and r.r (x moves in k_cg_dir, which reads p anyway).
 __global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ r,
                                                       const double* __restrict__ q_, int64_t n, int C,
                                                       const CgState* __restrict__ st,
                                                       double* __restrict__ partials) {
-  __shared__ double sh[kCgGroups * kMaxCgCols];
-  const int cpb = cg_cpb(C);
-  const int64_t nchunks = cg_chunks(n);
-  for (int64_t chunk0 = (int64_t)blockIdx.x * cpb; chunk0 < nchunks; chunk0 += (int64_t)gridDim.x * cpb) {
-    for (int q = threadIdx.x; q < cpb * kCgGroups * C; q += blockDim.x) {
-      const int c = q % C, gq = q / C;
-      const int64_t i0 = (chunk0 + gq / kCgGroups) * kCgChunk + (gq % kCgGroups) * kCgRowsPerGroup;
-      const double a = st->alpha[c];
-      double dot = 0.0;
+  extern __shared__ double dsh[];
+  cg_partials<kSuperUpdate>(n, C, partials, dsh, [=](int64_t i0, int c) {
+    const double a = st->alpha[c];
+    // all loads of the group first, then the stores
+    double qv[kCgRowsPerGroup], rv[kCgRowsPerGroup];
 #pragma unroll
-      for (int k = 0; k < kCgRowsPerGroup; ++k) {
-        const int64_t i = i0 + k;
-        if (i < n) {
-          const int64_t e = i * C + c;
-          const double rv = __builtin_fma(-a, q_[e], r[e]);
-          r[e] = rv;
-          dot += rv * rv;
-        }
-      }
-      sh[q] = dot;
+    for (int k = 0; k < kCgRowsPerGroup; ++k) {
+      const int64_t e = (i0 + k) * C + c;
+      qv[k] = i0 + k < n ? q_[e] : 0.0;
+      rv[k] = i0 + k < n ? r[e] : 0.0;
     }
-    cg_fold(sh, chunk0, cpb, nchunks, C, partials);
-  }
+    double dot = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCgRowsPerGroup; ++k) {
+      if (i0 + k < n) {
+        const double v = __builtin_fma(-a, qv[k], rv[k]);
+        r[(i0 + k) * C + c] = v;
+        dot += v * v;
+      }
+    }
+    return dot;
+  });
+}
+
+// The scalar step after a vector kernel, in one block of its own: the
+// kernel boundary makes every block's partials visible at the cost of one
+// L2 writeback per XCD, where a last-block fold inside a kernel of
+// thousands of blocks would pay one per block.
+constexpr int kScalarThreads = 1024;
+__global__ __launch_bounds__(kScalarThreads) void k_cg_scalar(CgHook h, int C) {
+  __shared__ double sh[kFold * kMaxCgCols];
+  cg_scalar_block(h.partials, h.nparts, C, h.st, h.mode, h.tol, sh);
 }
 
 // x += alpha p with this iteration's alpha (zero for a column that was
@@ -248,17 +206,22 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   const int64_t n = L->n, nC = n * C;
   int rc;
   if ((rc = dev_reserve(L, Lm->cgvec, sizeof(double) * 4 * nC, s))) return rc;
-  // partial sums: one row per chunk from the vector kernels, one row per tile from the slice
-  const int64_t vparts = cg_chunks(n);
-  const int64_t nparts = L->ntiles > vparts ? L->ntiles : vparts;
-  const size_t red_bytes = sizeof(double) * nparts * C + sizeof(CgState) + 256;
+  // partial sums: one row per superchunk from the vector kernels, one row
+  // per tile from the slice; then the scalar state, and the finished-block
+  // counter of the slice's last-block fold
+  const int64_t iparts = cg_supers(n, kSuperInit), uparts = cg_supers(n, kSuperUpdate);
+  const int64_t nparts = std::max(L->ntiles, iparts);
+  const size_t part_bytes = ((sizeof(double) * nparts * C + 255) / 256) * 256;
+  const size_t st_bytes = ((sizeof(CgState) + 255) / 256) * 256;
+  const size_t red_bytes = part_bytes + st_bytes + 256;
   if ((rc = dev_reserve(L, Lm->cgred, red_bytes, s))) return rc;
   double* x64 = (double*)Lm->cgvec.ptr;
   double* r = x64 + nC;
   double* p = r + nC;
   double* q = p + nC;
   double* partials = (double*)Lm->cgred.ptr;
-  CgState* st = (CgState*)((char*)Lm->cgred.ptr + ((sizeof(double) * nparts * C + 255) / 256) * 256);
+  CgState* st = (CgState*)((char*)Lm->cgred.ptr + part_bytes);
+  unsigned* counter = (unsigned*)((char*)Lm->cgred.ptr + part_bytes + st_bytes);
 
   int32_t* host = (int32_t*)pinned_scratch(sizeof(int32_t) * 3 * kMaxCgCols);
   if (!host) {
@@ -267,47 +230,44 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   }
 
   const dim3 block(kBlock);
-  const dim3 vgrid((unsigned)std::min<int64_t>((vparts + cg_cpb(C) - 1) / cg_cpb(C), 65536));
-  const dim3 grid(kRedBlocks);
+  const dim3 igrid((unsigned)std::min<int64_t>(iparts, 65536));
+  const dim3 ugrid((unsigned)std::min<int64_t>(uparts, 65536));
+  const size_t vlds = cg_vec_lds(C);
   const dim3 dgrid((unsigned)std::min<int64_t>((nC / 2 + kBlock - 1) / kBlock + 1, 65536));
+  const CgHook h_start{partials, iparts, st, counter, (int)SM_START, (double)tol};
+  const CgHook h_alpha{partials, L->ntiles, st, counter, (int)SM_ALPHA, (double)tol};
+  const CgHook h_beta{partials, uparts, st, counter, (int)SM_BETA, (double)tol};
+  if ((rc = launch_fill_u32(counter, 1, 0u, s))) return rc;
   {
     ProfScope ps(KK_CG_INIT, s);
-    hipLaunchKernelGGL(k_cg_init, vgrid, block, 0, s, b, (const uint32_t*)L->perm.ptr, x64, r, p, n, C,
+    hipLaunchKernelGGL(k_cg_init, igrid, block, vlds, s, b, (const uint32_t*)L->perm.ptr, x64, r, p, n, C,
                        L->solve_rows, partials);
     SGP_LAUNCH_CHECK("k_cg_init");
   }
   {
     ProfScope ps(KK_CG_SCALAR, s);
-    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, partials, vparts, C, st,
-                       (int)SM_START, (double)tol);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, h_start, C);
     SGP_LAUNCH_CHECK("k_cg_scalar");
   }
-  // One iteration: q = A p (with the p.q partials from the slice), alpha,
-  // x and r, convergence and beta, p. Nothing here talks to the host, so a
-  // block of iterations can be recorded as a graph.
+  // One iteration: q = A p (the slice's last block turns p.q into alpha),
+  // r and its norm, convergence and beta, then x and p. Nothing here talks to the host, so a block of iterations
+  // can be recorded as a graph.
   auto iterate = [&](hipStream_t st_) -> int {
-    int rc_ = mvm_cg(L, p, C, q, st_, (double)noise, partials);
+    int rc_ = mvm_cg(L, p, C, q, st_, (double)noise, &h_alpha);
     if (rc_) return rc_;
     {
-      ProfScope ps(KK_CG_SCALAR, st_);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, partials, L->ntiles, C, st,
-                         (int)SM_ALPHA, (double)tol);
-      SGP_LAUNCH_CHECK("k_cg_scalar");
-    }
-    {
       ProfScope ps(KK_CG_UPDATE, st_);
-      hipLaunchKernelGGL(k_cg_update, vgrid, block, 0, st_, r, q, n, C, st, partials);
+      hipLaunchKernelGGL(k_cg_update, ugrid, block, vlds, st_, r, q, n, C, (const CgState*)st, partials);
       SGP_LAUNCH_CHECK("k_cg_update");
     }
     {
       ProfScope ps(KK_CG_SCALAR, st_);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, partials, vparts, C,
-                         st, (int)SM_BETA, (double)tol);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, h_beta, C);
       SGP_LAUNCH_CHECK("k_cg_scalar");
     }
     {
       ProfScope ps(KK_CG_DIR, st_);
-      hipLaunchKernelGGL(k_cg_dir, dgrid, block, 0, st_, x64, r, p, nC, C, st);
+      hipLaunchKernelGGL(k_cg_dir, dgrid, block, 0, st_, x64, r, p, nC, C, (const CgState*)st);
       SGP_LAUNCH_CHECK("k_cg_dir");
     }
     return SGP_OK;

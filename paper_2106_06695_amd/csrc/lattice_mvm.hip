@@ -29,6 +29,7 @@
 // Row ranges of consecutive blocks go to the same XCD (blocks are dealt
 // round-robin over the 8 XCDs), so tiles that share lattice points share
 // an L2.
+#include "cg_step.h"
 #include "sgp_internal.h"
 
 namespace sgp {
@@ -602,7 +603,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
     const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_verts,
     const uint16_t* __restrict__ loc, const float* __restrict__ ws, const TU* __restrict__ U,
     TU* __restrict__ out, const uint32_t* __restrict__ perm, const TU* __restrict__ p,
-    double* __restrict__ partials, const uint32_t* __restrict__ mperm, SliceArgs<TU> a) {
+    CgHook hook, const uint32_t* __restrict__ mperm, SliceArgs<TU> a) {
   using S = TileShape<TU, G, kSliceBlock>;
   extern __shared__ __align__(16) unsigned char smem[];
   TU* lu = (TU*)smem;
@@ -633,16 +634,21 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
       ur[u] = U[(int64_t)vj[u] * a.C + (c < a.C ? c : a.C - 1)];
     }
   };
+  // A tile's first-chunk row indices are requested early (fetch_index) and
+  // its entries and rows later (fetch), so the rows never wait for them.
+  auto fetch_index = [&](int64_t item) {
+    const int64_t t = item / a.chunks;
+    const int64_t p0 = t * a.P;
+    np = (int)(a.n - p0 < a.P ? a.n - p0 : a.P);
+    q0 = tile_off[t];
+    nq = tile_off[t + 1] - q0;
+    load_index(0, nq < RC ? nq : RC, tile_verts + q0);
+  };
   auto fetch = [&](int64_t item) {
     const int64_t t = item / a.chunks;
     const int ch = (int)(item - t * a.chunks);
     const int64_t p0 = t * a.P;
-    np = (int)(a.n - p0 < a.P ? a.n - p0 : a.P);
     const int ne = np * a.D;
-    q0 = tile_off[t];
-    nq = tile_off[t + 1] - q0;
-    // row indices first: the rows wait only for them, not for the entries
-    load_index(0, nq < RC ? nq : RC, tile_verts + q0);
     const float* gw = ws + p0 * a.D;
     const uint16_t* gsl = loc + p0 * a.D;
 #pragma unroll
@@ -671,7 +677,10 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
 
   int64_t item, end, step;
   xcd_items(a.items, &item, &end, &step);
-  if (item < end) fetch(item);
+  if (item < end) {
+    fetch_index(item);
+    fetch(item);
+  }
   for (; item < end; item += step) {
     const int64_t t = item / a.chunks;
     const int ch = (int)(item - t * a.chunks);
@@ -714,6 +723,8 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
         }
       }
     }
+    const bool next = item + step < end;
+    if (next) fetch_index(item + step);
     TU acc[S::PPG][S::VW];
 #pragma unroll
     for (int k = 0; k < S::PPG; ++k)
@@ -726,10 +737,11 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
         load_index(r0, nr, tile_verts + cur_q0);
         load_rows(ch);
         stage_rows(nr);
+        if (next) fetch_index(item + step);  // the indices were overwritten
       }
       __syncthreads();
       // the next tile's entries and first rows load during the last chunk
-      if (r0 + RC >= cur_nq && item + step < end) fetch(item + step);
+      if (r0 + RC >= cur_nq && next) fetch(item + step);
       if (live) {
 #pragma unroll
         for (int k = 0; k < S::PPG; ++k) {
@@ -737,7 +749,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
           if (lp < cur_np) {
             const int eb = lp * a.D;
             // EB entries at a time: slots and weights, then their rows
-            constexpr int EB = S::VW * sizeof(TU) >= 32 ? 2 : 4;
+            constexpr int EB = S::VW * sizeof(TU) >= 32 ? (CG ? 1 : 2) : 4;
             for (int j0 = 0; j0 < a.D; j0 += EB) {
               int sv[EB];
               TU wv[EB];
@@ -819,11 +831,13 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
         if (tid < 16 && cs + tid < G && ch * G + cs + tid < a.C) {
           double v = 0.0;
           for (int blk = 0; blk < 16; ++blk) v += sh2[blk * 16 + tid];
-          partials[t * a.C + ch * G + cs + tid] = v;
+          hook.partials[t * a.C + ch * G + cs + tid] = v;
         }
       }
     }
   }
+  // CG: the last block to finish folds the tiles' p . q into alpha
+  if constexpr (CG) cg_finish(hook, a.C, (double*)smem);
 }
 
 
@@ -897,7 +911,7 @@ void split_rows(int64_t rows, int R, int64_t cap, unsigned* blocks, int64_t* row
 
 template <typename TU, int G>
 int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out, hipStream_t s,
-          TU noise, const TU* p, double* partials) {
+          TU noise, const TU* p, const CgHook* hook) {
   const int d = L->d, D = d + 1, T = 2 * L->order;
   const int64_t m = L->m, mC = m * C;
   TU* U0 = (TU*)L->ubuf.ptr;
@@ -986,21 +1000,21 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   la.cvec = (C % Vec16<TU>::N == 0 && aligned16(out) && (!p || aligned16(p))) ? 1 : 0;
   la.scale = scale;
   la.noise = noise;
-  la.mrows = partials ? L->solve_rows : 0;
+  la.mrows = hook ? L->solve_rows : 0;
   la.lds = slice_lds<TU, G>(P, D, maxq);
   const int32_t* toff = (const int32_t*)L->tile_off.ptr;
   const int32_t* tverts = (const int32_t*)L->tile_verts.ptr;
   const uint16_t* loc = (const uint16_t*)L->loc.ptr;
   const float* ws = (const float*)L->ws.ptr;
   const uint32_t* mperm = (const uint32_t*)L->perm.ptr;
-  if (partials) {
+  if (hook) {
     const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, true>, kSliceBlock, la.lds.total, la.items);
     hipLaunchKernelGGL((k_slice_tile<TU, G, true>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
-                       tverts, loc, ws, (const TU*)cur[0], out, perm, p, partials, mperm, la);
+                       tverts, loc, ws, (const TU*)cur[0], out, perm, p, *hook, mperm, la);
   } else {
     const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, false>, kSliceBlock, la.lds.total, la.items);
     hipLaunchKernelGGL((k_slice_tile<TU, G, false>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
-                       tverts, loc, ws, (const TU*)cur[0], out, perm, (const TU*)nullptr, (double*)nullptr,
+                       tverts, loc, ws, (const TU*)cur[0], out, perm, (const TU*)nullptr, CgHook{},
                        mperm, la);
   }
   SGP_LAUNCH_CHECK("k_slice_tile");
@@ -1025,18 +1039,18 @@ int chunk_lanes(const sgp_lattice* L, int C, size_t elem) {
 
 template <typename TU>
 int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out,
-                 hipStream_t s, TU noise, const TU* p, double* partials) {
+                 hipStream_t s, TU noise, const TU* p, const CgHook* hook) {
   int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf,
                        sizeof(TU) * (4 * L->m + L->npiece + 2 * gather_ranges(L)) * (size_t)C, s);
   if (rc) return rc;
   switch (chunk_lanes(L, C, sizeof(TU))) {
-    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, partials);
-    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, p, partials);
-    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, p, partials);
-    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, p, partials);
-    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, p, partials);
-    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, p, partials);
-    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, p, partials);
+    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, hook);
+    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, p, hook);
+    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, p, hook);
+    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, p, hook);
+    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, p, hook);
+    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, p, hook);
+    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, p, hook);
   }
 }
 
@@ -1048,8 +1062,8 @@ int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_
 }
 
 int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t s, double noise,
-           double* partials) {
-  return mvm_dispatch<double>(L, p, nullptr, C, q, s, noise, p, partials);
+           const CgHook* hook) {
+  return mvm_dispatch<double>(L, p, nullptr, C, q, s, noise, p, hook);
 }
 
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s) {

@@ -207,8 +207,9 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, i
 // fp32 values, fp32 lattice accumulation (lattice_mvm)
 int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s);
 // fp64 values and accumulation with the CG epilogue: q = A p, partial sums of p.q
+struct CgHook;
 int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t s, double noise,
-           double* partials);
+           const CgHook* hook);
 // fp64 values and accumulation, internal point order, no epilogue
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s);
 }  // namespace sgp
