@@ -518,126 +518,177 @@ __global__ __launch_bounds__(kBlock) void k_nbr_internal(const int32_t* __restri
   }
 }
 
-// Tiles: key = (tile of the sorted point, internal vertex); after a stable
-// sort by key, equal keys form a "run" = one lattice point of one tile, with
-// its entries in sorted-point order.
-__global__ __launch_bounds__(kBlock) void k_tile_keys(const sgp_entry* __restrict__ pm, int64_t L,
-                                                      int D, int P, int mb,
-                                                      unsigned long long* __restrict__ key,
-                                                      uint32_t* __restrict__ val) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += stride) {
-    const unsigned long long tile = (unsigned long long)((e / D) / P);
-    key[e] = (tile << mb) | (unsigned long long)(uint32_t)pm[e].j;
-    val[e] = (uint32_t)e;
+// ---------------------------------------------------------------------------
+// Tiles of P consecutive sorted points. Within a tile, entries are ordered by
+// (internal lattice point, entry): equal lattice points form a "run" (one
+// lattice point of one tile, its entries in sorted-point order), and runs are
+// cut into pieces of at most K entries for the splat. A tile holds at most
+// kTileSlots entries, so one block sorts it in LDS (bitonic network over the
+// unique keys (lattice point << 12) | entry), which gives the same order as a
+// stable sort of all entries by (tile, lattice point).
+constexpr int kTileThreads = 1024;
+constexpr int kTileSlots = 4096;
+constexpr int kTileSpan = kTileSlots / kTileThreads;  // consecutive slots per thread
+
+struct TileSort {
+  unsigned long long key[kTileSlots];
+  int32_t rstart[kTileSlots];  // sorted position of each run's first entry
+  int32_t wsum[kTileThreads / 64];
+};
+
+// Block-wide exclusive scan of one count per thread; *total gets the sum.
+__device__ inline int tile_scan(int v, int32_t* wsum, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
   }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int i = 0; i < kTileThreads / 64; ++i) {
+    const int c = wsum[i];
+    before += i < w ? c : 0;
+    all += c;
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_run_flags(const unsigned long long* __restrict__ key,
-                                                      int64_t L, uint32_t* __restrict__ flag) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride)
-    flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1u : 0u;
-}
-
-// Run q of sorted entry p is (exclusive count of run starts before p) +
-// flag - 1. Entry p is the (p - tile * P * D)-th entry of its tile, since a
-// tile's entries are exactly those of its points. Writes each run's lattice
-// point, the per-entry (point within the tile, weight) in run order, and
-// the tile offsets.
-__global__ __launch_bounds__(kBlock) void k_run_fill(const unsigned long long* __restrict__ key,
-                                                     const uint32_t* __restrict__ val,
-                                                     const uint32_t* __restrict__ flag,
-                                                     const uint32_t* __restrict__ ex,
-                                                     const sgp_entry* __restrict__ pm, int64_t L,
-                                                     int D, int P, int mb, int64_t ntiles,
-                                                     int32_t* __restrict__ tile_verts,
-                                                     uint8_t* __restrict__ ent_lp,
-                                                     float* __restrict__ ent_w,
-                                                     int32_t* __restrict__ tile_off) {
-  const unsigned long long jmask = (1ull << mb) - 1ull;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride) {
-    const unsigned long long k = key[p];
-    const uint32_t e = val[p];
-    const uint32_t f = flag[p];
-    const int64_t q = (int64_t)ex[p] + f - 1;
-    const int64_t tile = (int64_t)(k >> mb);
-    ent_lp[p] = (uint8_t)((int64_t)(e / (uint32_t)D) - tile * P);
-    ent_w[p] = pm[e].w;
-    if (f) {
-      tile_verts[q] = (int32_t)(k & jmask);
-      if (p == 0 || (key[p - 1] >> mb) != (unsigned long long)tile) tile_off[tile] = (int32_t)q;
+// Sort the N (a power of two) keys ascending.
+__device__ inline void tile_bitonic(unsigned long long* key, int N) {
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N / 2; i += kTileThreads) {
+        const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+        const int hi = lo + j;
+        const unsigned long long x = key[lo], y = key[hi];
+        if ((x > y) == ((lo & k) == 0)) {
+          key[lo] = y;
+          key[hi] = x;
+        }
+      }
+      __syncthreads();
     }
-    if (p == L - 1) tile_off[ntiles] = (int32_t)(q + 1);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_loc_fill(const unsigned long long* __restrict__ key,
-                                                     const uint32_t* __restrict__ val,
-                                                     const uint32_t* __restrict__ flag,
-                                                     const uint32_t* __restrict__ ex,
-                                                     const int32_t* __restrict__ tile_off,
-                                                     const sgp_entry* __restrict__ pm, int64_t L,
-                                                     int mb, uint16_t* __restrict__ loc,
-                                                     float* __restrict__ ws) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride) {
-    const int64_t q = (int64_t)ex[p] + flag[p] - 1;
-    const int64_t tile = (int64_t)(key[p] >> mb);
-    const uint32_t e = val[p];
-    loc[e] = (uint16_t)(q - tile_off[tile]);
-    ws[e] = pm[e].w;
+// Run and piece starts of this thread's kTileSpan sorted positions, and
+// their ranks within the tile. key[] holds the tile's sorted keys.
+struct TileRanks {
+  int q[kTileSpan];   // run of each position
+  int qp[kTileSpan];  // piece of each position, where it starts one (else -1)
+  bool rs[kTileSpan];
+  int runs, pieces;
+};
+__device__ inline void tile_ranks(TileSort& T, int ne, int K, TileRanks& r) {
+  const int i0 = threadIdx.x * kTileSpan;
+  int c = 0;
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    const int i = i0 + u;
+    r.rs[u] = i < ne && (i == 0 || (T.key[i] >> 12) != (T.key[i - 1] >> 12));
+    c += r.rs[u] ? 1 : 0;
+  }
+  int q = tile_scan(c, T.wsum, &r.runs) - 1;
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    q += r.rs[u] ? 1 : 0;
+    r.q[u] = q;
+    if (r.rs[u]) T.rstart[q] = i0 + u;
+  }
+  __syncthreads();
+  bool ps[kTileSpan];
+  c = 0;
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    const int i = i0 + u;
+    ps[u] = i < ne && (i - T.rstart[r.q[u]]) % K == 0;
+    c += ps[u] ? 1 : 0;
+  }
+  int qp = tile_scan(c, T.wsum, &r.pieces);
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    r.qp[u] = ps[u] ? qp : -1;
+    qp += ps[u] ? 1 : 0;
   }
 }
 
-// The splat reduces each run sequentially, so a run that many points of a
-// tile share would serialise the tile: runs are cut into pieces of at most
-// K entries, each reduced on its own and summed with the other partial rows
-// of its lattice point. First the start of every run ...
-__global__ __launch_bounds__(kBlock) void k_run_starts(const uint32_t* __restrict__ flag,
-                                                       const uint32_t* __restrict__ ex, int64_t L,
-                                                       uint32_t* __restrict__ start) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride)
-    if (flag[p]) start[ex[p]] = (uint32_t)p;
-}
-
-// ... then a piece starts where the offset within the run is a multiple of K
-// (flag rewritten in place, each entry by its own thread).
-__global__ __launch_bounds__(kBlock) void k_piece_flags(uint32_t* __restrict__ flag,
-                                                        const uint32_t* __restrict__ ex,
-                                                        const uint32_t* __restrict__ start, int64_t L,
-                                                        int K) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride) {
-    const uint32_t r = ex[p] + flag[p] - 1;
-    flag[p] = ((p - (int64_t)start[r]) % K == 0) ? 1u : 0u;
+// Pass 1: sort each tile, keep the order (entry within the tile per sorted
+// position) and count its runs and pieces.
+__global__ __launch_bounds__(kTileThreads) void k_tile_order(const sgp_entry* __restrict__ pm, int64_t n,
+                                                             int D, int P, int K,
+                                                             uint16_t* __restrict__ ord,
+                                                             uint32_t* __restrict__ runs,
+                                                             uint32_t* __restrict__ pieces) {
+  __shared__ TileSort T;
+  const int64_t t = blockIdx.x;
+  const int64_t p0 = t * P;
+  const int ne = (int)((n - p0 < P ? n - p0 : P) * D);
+  const int64_t base = p0 * D;
+  int N = 64;
+  while (N < ne) N <<= 1;
+  for (int i = threadIdx.x; i < N; i += kTileThreads)
+    T.key[i] = i < ne ? ((unsigned long long)(uint32_t)pm[base + i].j << 12) | (unsigned)i : ~0ull;
+  __syncthreads();
+  tile_bitonic(T.key, N);
+  TileRanks r;
+  tile_ranks(T, ne, K, r);
+  for (int i = threadIdx.x; i < ne; i += kTileThreads) ord[base + i] = (uint16_t)(T.key[i] & 4095u);
+  if (threadIdx.x == 0) {
+    runs[t] = (uint32_t)r.runs;
+    pieces[t] = (uint32_t)r.pieces;
   }
 }
 
-// Pieces: first entry relative to the tile, lattice point, first piece of
-// each tile.
-__global__ __launch_bounds__(kBlock) void k_piece_fill(const unsigned long long* __restrict__ key,
-                                                       const uint32_t* __restrict__ flag,
-                                                       const uint32_t* __restrict__ ex, int64_t L,
-                                                       int D, int P, int mb, int64_t ntiles,
-                                                       uint16_t* __restrict__ run_rel,
-                                                       int32_t* __restrict__ piece_vert,
-                                                       int32_t* __restrict__ stile_off) {
-  const unsigned long long jmask = (1ull << mb) - 1ull;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < L; p += stride) {
-    const unsigned long long k = key[p];
-    const uint32_t f = flag[p];
-    const int64_t q = (int64_t)ex[p] + f - 1;
-    const int64_t tile = (int64_t)(k >> mb);
-    if (f) {
-      piece_vert[q] = (int32_t)(k & jmask);
-      run_rel[q] = (uint16_t)(p - tile * (int64_t)P * D);
-      if (p == 0 || (key[p - 1] >> mb) != (unsigned long long)tile) stile_off[tile] = (int32_t)q;
+// Pass 2, with each tile's first run and piece known: the slice's runs
+// (lattice point per run, run slot per entry in point order), the splat's
+// entries in run order (point within the tile, weight) and its pieces
+// (first entry relative to the tile, lattice point).
+__global__ __launch_bounds__(kTileThreads) void k_tile_fill(const sgp_entry* __restrict__ pm,
+                                                            const uint16_t* __restrict__ ord, int64_t n,
+                                                            int D, int P, int K,
+                                                            const int32_t* __restrict__ tile_off,
+                                                            const int32_t* __restrict__ stile_off,
+                                                            int32_t* __restrict__ tile_verts,
+                                                            uint16_t* __restrict__ loc,
+                                                            float* __restrict__ ws,
+                                                            uint8_t* __restrict__ ent_lp,
+                                                            float* __restrict__ ent_w,
+                                                            uint16_t* __restrict__ run_rel,
+                                                            int32_t* __restrict__ piece_vert) {
+  __shared__ TileSort T;
+  const int64_t t = blockIdx.x;
+  const int64_t p0 = t * P;
+  const int ne = (int)((n - p0 < P ? n - p0 : P) * D);
+  const int64_t base = p0 * D;
+  for (int i = threadIdx.x; i < ne; i += kTileThreads) {
+    const unsigned le = ord[base + i];
+    T.key[i] = ((unsigned long long)(uint32_t)pm[base + le].j << 12) | le;
+    ws[base + i] = pm[base + i].w;
+  }
+  __syncthreads();
+  TileRanks r;
+  tile_ranks(T, ne, K, r);
+  const int64_t q0 = tile_off[t], qp0 = stile_off[t];
+  const int i0 = threadIdx.x * kTileSpan;
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    const int i = i0 + u;
+    if (i >= ne) break;
+    const unsigned long long k = T.key[i];
+    const int32_t j = (int32_t)(k >> 12);
+    const unsigned le = (unsigned)(k & 4095u);
+    ent_lp[base + i] = (uint8_t)(le / (unsigned)D);
+    ent_w[base + i] = pm[base + le].w;
+    loc[base + le] = (uint16_t)r.q[u];
+    if (r.rs[u]) tile_verts[q0 + r.q[u]] = j;
+    if (r.qp[u] >= 0) {
+      run_rel[qp0 + r.qp[u]] = (uint16_t)i;
+      piece_vert[qp0 + r.qp[u]] = j;
     }
-    if (p == L - 1) stile_off[ntiles] = (int32_t)(q + 1);
   }
 }
 
@@ -734,7 +785,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   int rc;
   enum {
     T_R0, T_RANK, T_SLOT, T_TAB, T_FIRST, T_COUNTS, T_OFFS, T_WORDS, T_IDX, T_W, T_NBRC,
-    T_SLOTS, T_FIRST2, T_CAN2INT, T_KA, T_KB, T_VA, T_VB, T_SORTTMP, T_PM, T_SUB
+    T_SLOTS, T_FIRST2, T_CAN2INT, T_KA, T_KB, T_VA, T_VB, T_SORTTMP, T_PM, T_SUB, T_ORD, T_CNT
   };
   if ((rc = tr.alloc(T_R0, sizeof(int32_t) * n * d))) return rc;
   if ((rc = tr.alloc(T_RANK, sizeof(uint8_t) * n * d))) return rc;
@@ -872,8 +923,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   if ((rc = tr.alloc(T_SLOTS, sizeof(int32_t) * Lel))) return rc;
   if ((rc = tr.alloc(T_FIRST2, sizeof(uint32_t) * cap))) return rc;
   if ((rc = tr.alloc(T_CAN2INT, sizeof(int32_t) * m))) return rc;
-  if ((rc = tr.alloc(T_KA, sizeof(unsigned long long) * Lel))) return rc;
-  if ((rc = tr.alloc(T_KB, sizeof(unsigned long long) * Lel))) return rc;
+  // sort buffers: 64-bit point keys (n), then 32-bit piece keys (at most Lel)
+  const size_t kbytes = std::max(sizeof(unsigned long long) * n, sizeof(uint32_t) * Lel);
+  if ((rc = tr.alloc(T_KA, kbytes))) return rc;
+  if ((rc = tr.alloc(T_KB, kbytes))) return rc;
   if ((rc = tr.alloc(T_PM, sizeof(sgp_entry) * Lel))) return rc;
   if ((rc = tr.alloc(T_VA, sizeof(uint32_t) * Lel))) return rc;
   if ((rc = tr.alloc(T_VB, sizeof(uint32_t) * Lel))) return rc;
@@ -954,90 +1007,69 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     const int64_t ntiles = (n + P - 1) / P;
     L->ntiles = ntiles;
     const int mb = bits_for((uint64_t)(m - 1));
-    const int tb = bits_for((uint64_t)(ntiles - 1));
-    unsigned long long* ka = (unsigned long long*)tr.ptr[T_KA];
-    unsigned long long* kb = (unsigned long long*)tr.ptr[T_KB];
+    if ((rc = tr.alloc(T_ORD, sizeof(uint16_t) * Lel))) return rc;
+    if ((rc = tr.alloc(T_CNT, sizeof(uint32_t) * 2 * ntiles))) return rc;
+    uint16_t* ord = (uint16_t*)tr.ptr[T_ORD];
+    uint32_t* runs = (uint32_t*)tr.ptr[T_CNT];
+    uint32_t* pieces = runs + ntiles;
+    if ((rc = dev_alloc(L->tile_off, sizeof(int32_t) * (ntiles + 1), st))) return rc;
+    if ((rc = dev_alloc(L->stile_off, sizeof(int32_t) * (ntiles + 1), st))) return rc;
+    int32_t* tile_off = (int32_t*)L->tile_off.ptr;
+    int32_t* stile_off = (int32_t*)L->stile_off.ptr;
     {
       ProfScope ps(KK_ORDER, st);
-      hipLaunchKernelGGL(k_tile_keys, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st,
-                         (const sgp_entry*)tr.ptr[T_PM], Lel, D, P, mb, ka, va);
-      SGP_LAUNCH_CHECK("k_tile_keys");
+      hipLaunchKernelGGL(k_tile_order, dim3((unsigned)ntiles), dim3(kTileThreads), 0, st,
+                         (const sgp_entry*)tr.ptr[T_PM], n, D, P, kPiece, ord, runs, pieces);
+      SGP_LAUNCH_CHECK("k_tile_order");
     }
-    bool in_alt = false;
-    if ((rc = radix_sort_pairs<unsigned long long>(ka, va, kb, vb, Lel, mb + tb, sort_tmp, st, &in_alt)))
+    // first run and first piece of every tile; the totals land in entry ntiles
+    if ((rc = scan_exclusive_u32(runs, (uint32_t*)tile_off, ntiles, (uint32_t*)tile_off + ntiles,
+                                 sort_tmp, st)))
       return rc;
-    const unsigned long long* sk = in_alt ? kb : ka;
-    const uint32_t* sv = in_alt ? vb : va;
-    uint32_t* flag = (uint32_t*)(in_alt ? ka : kb);  // the other key buffer: 2 x Lel words
-    uint32_t* ex = flag + Lel;
-    {
-      ProfScope ps(KK_ORDER, st);
-      hipLaunchKernelGGL(k_run_flags, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, Lel,
-                         flag);
-      SGP_LAUNCH_CHECK("k_run_flags");
-    }
-    if ((rc = scan_exclusive_u32(flag, ex, Lel, words + 3, sort_tmp, st))) return rc;
-    SGP_HIP(hipMemcpyAsync(host_word + 3, words + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    if ((rc = scan_exclusive_u32(pieces, (uint32_t*)stile_off, ntiles, (uint32_t*)stile_off + ntiles,
+                                 sort_tmp, st)))
+      return rc;
+    // longest run list and piece list of a tile (they size the LDS stages)
+    std::vector<int32_t> toff(ntiles + 1), soff(ntiles + 1);
+    SGP_HIP(hipMemcpyAsync(toff.data(), tile_off, sizeof(int32_t) * (ntiles + 1), hipMemcpyDeviceToHost, st));
+    SGP_HIP(hipMemcpyAsync(soff.data(), stile_off, sizeof(int32_t) * (ntiles + 1), hipMemcpyDeviceToHost, st));
     SGP_HIP(hipStreamSynchronize(st));
-    const int64_t Q = host_word[3];
-    if (Q < 1 || Q > Lel) {
-      set_error("lattice_build: inconsistent tile run count %lld", (long long)Q);
+    const int64_t Q = toff[ntiles], Qs = soff[ntiles];
+    if (Q < 1 || Q > Lel || Qs < Q || Qs > Lel) {
+      set_error("lattice_build: inconsistent run / piece counts %lld / %lld", (long long)Q, (long long)Qs);
       return SGP_EHASH;
     }
+    int mx = 0, msx = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      mx = std::max(mx, toff[t + 1] - toff[t]);
+      msx = std::max(msx, soff[t + 1] - soff[t]);
+    }
     L->nrun = Q;
-    if ((rc = dev_alloc(L->tile_off, sizeof(int32_t) * (ntiles + 1), st))) return rc;
+    L->npiece = Qs;
+    L->max_tile_runs = mx;
+    L->max_tile_pieces = msx;
     if ((rc = dev_alloc(L->tile_verts, sizeof(int32_t) * Q, st))) return rc;
     // four spare bytes: the splat reads entry points four at a time
     if ((rc = dev_alloc(L->ent_lp, sizeof(uint8_t) * (Lel + 4), st))) return rc;
     if ((rc = dev_alloc(L->ent_w, sizeof(float) * Lel, st))) return rc;
-    {
-      ProfScope ps(KK_ORDER, st);
-      hipLaunchKernelGGL(k_run_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, sv,
-                         flag, ex, (const sgp_entry*)tr.ptr[T_PM], Lel, D, P, mb, ntiles,
-                         (int32_t*)L->tile_verts.ptr, (uint8_t*)L->ent_lp.ptr, (float*)L->ent_w.ptr,
-                         (int32_t*)L->tile_off.ptr);
-      SGP_LAUNCH_CHECK("k_run_fill");
-      hipLaunchKernelGGL(k_loc_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, sv,
-                         flag, ex, (const int32_t*)L->tile_off.ptr, (const sgp_entry*)tr.ptr[T_PM],
-                         Lel, mb, (uint16_t*)L->loc.ptr, (float*)L->ws.ptr);
-      SGP_LAUNCH_CHECK("k_loc_fill");
-    }
-    // the splat's pieces of at most kPiece entries per run
-    if ((rc = tr.alloc(T_SUB, sizeof(uint32_t) * Lel))) return rc;
-    uint32_t* sub = (uint32_t*)tr.ptr[T_SUB];
-    {
-      ProfScope ps(KK_ORDER, st);
-      hipLaunchKernelGGL(k_run_starts, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, flag, ex,
-                         Lel, sub);
-      SGP_LAUNCH_CHECK("k_run_starts");
-      hipLaunchKernelGGL(k_piece_flags, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, flag, ex,
-                         (const uint32_t*)sub, Lel, kPiece);
-      SGP_LAUNCH_CHECK("k_piece_flags");
-    }
-    if ((rc = scan_exclusive_u32(flag, ex, Lel, words + 3, sort_tmp, st))) return rc;
-    SGP_HIP(hipMemcpyAsync(host_word + 3, words + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    SGP_HIP(hipStreamSynchronize(st));
-    const int64_t Qs = host_word[3];
-    if (Qs < Q || Qs > Lel) {
-      set_error("lattice_build: inconsistent piece count %lld", (long long)Qs);
-      return SGP_EHASH;
-    }
-    L->npiece = Qs;
-    if ((rc = dev_alloc(L->stile_off, sizeof(int32_t) * (ntiles + 1), st))) return rc;
     if ((rc = dev_alloc(L->run_rel, sizeof(uint16_t) * Qs, st))) return rc;
     if ((rc = dev_alloc(L->occ_ptr, sizeof(int32_t) * (m + 1), st))) return rc;
     if ((rc = dev_alloc(L->run_dst, sizeof(int32_t) * Qs, st))) return rc;
     if ((rc = dev_alloc(L->row_vert, sizeof(int32_t) * Qs, st))) return rc;
+    if ((rc = tr.alloc(T_SUB, sizeof(uint32_t) * Qs))) return rc;
+    uint32_t* sub = (uint32_t*)tr.ptr[T_SUB];  // lattice point of each piece
     {
       ProfScope ps(KK_ORDER, st);
-      hipLaunchKernelGGL(k_piece_fill, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, sk, flag,
-                         ex, Lel, D, P, mb, ntiles, (uint16_t*)L->run_rel.ptr, (int32_t*)sub,
-                         (int32_t*)L->stile_off.ptr);
-      SGP_LAUNCH_CHECK("k_piece_fill");
+      hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)ntiles), dim3(kTileThreads), 0, st,
+                         (const sgp_entry*)tr.ptr[T_PM], (const uint16_t*)ord, n, D, P, kPiece,
+                         (const int32_t*)tile_off, (const int32_t*)stile_off, (int32_t*)L->tile_verts.ptr,
+                         (uint16_t*)L->loc.ptr, (float*)L->ws.ptr, (uint8_t*)L->ent_lp.ptr,
+                         (float*)L->ent_w.ptr, (uint16_t*)L->run_rel.ptr, (int32_t*)sub);
+      SGP_LAUNCH_CHECK("k_tile_fill");
     }
     // pieces grouped by lattice point (32-bit keys; reuses the sort buffers)
-    uint32_t* k32a = (uint32_t*)(in_alt ? kb : ka);
-    uint32_t* k32b = k32a + Qs;
+    uint32_t* k32a = (uint32_t*)tr.ptr[T_KA];
+    uint32_t* k32b = (uint32_t*)tr.ptr[T_KB];
     {
       ProfScope ps(KK_ORDER, st);
       hipLaunchKernelGGL(k_occ_keys, dim3(grid_for(Qs, kBlock, 16384)), dim3(kBlock), 0, st,
@@ -1053,20 +1085,6 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
                          (int32_t*)L->run_dst.ptr, (int32_t*)L->row_vert.ptr);
       SGP_LAUNCH_CHECK("k_occ_fill");
     }
-    // longest run list and piece list of a tile (size the LDS stages)
-    std::vector<int32_t> toff(ntiles + 1), soff(ntiles + 1);
-    SGP_HIP(hipMemcpyAsync(toff.data(), L->tile_off.ptr, sizeof(int32_t) * (ntiles + 1),
-                           hipMemcpyDeviceToHost, st));
-    SGP_HIP(hipMemcpyAsync(soff.data(), L->stile_off.ptr, sizeof(int32_t) * (ntiles + 1),
-                           hipMemcpyDeviceToHost, st));
-    SGP_HIP(hipStreamSynchronize(st));
-    int mx = 0, ms = 0;
-    for (int64_t t = 0; t < ntiles; ++t) {
-      mx = std::max(mx, toff[t + 1] - toff[t]);
-      ms = std::max(ms, soff[t + 1] - soff[t]);
-    }
-    L->max_tile_runs = mx;
-    L->max_tile_pieces = ms;
   }
   SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost, st));
   SGP_HIP(hipStreamSynchronize(st));
