@@ -1,20 +1,26 @@
 // Lattice construction (Section 3.2, Splat and Blur):
-//   k_simplex_insert  elevation, enclosing simplex, barycentric weights, and
-//                     insertion of every simplex vertex into a hash table
+//   k_elevate         elevation, enclosing simplex and barycentric weights
+//                     of every point
+//   (points sorted by their remainder-0 lattice point, then in tiles of P
+//   consecutive sorted points)
+//   k_tile_insert     hash every simplex vertex of a tile, insert each
+//                     distinct one into a hash table once, and keep per slot
+//                     its first entry in caller order and in sorted order
 //   k_count_first / k_scan / k_compact
 //                     number the distinct vertices by first occurrence in
-//                     the (point, vertex) order and write their keys
-//   k_resolve         vertex -> lattice index for every (point, vertex),
-//                     with an exact key check that detects hash collisions
+//                     the caller's (point, vertex) order and write their keys
 //   k_neighbors       neighbours of every lattice point along the d+1
 //                     lattice directions at offsets -r..r
+//   internal numbering by first touch in sorted order, then per tile the
+//   runs (k_tile_order / k_tile_fill) and the pieces grouped by lattice point
 //
 // Hash table: open addressing with linear probing over 64-bit key hashes
 // (a slot is claimed by one 64-bit compare-and-swap, so insertion is
 // lock-free and never waits on another lane). Two distinct keys with equal
-// hashes would share a slot; k_resolve compares every vertex key with the
-// stored key of its slot and the host rebuilds with a new seed if any
-// differ, so the final lattice is exact.
+// hashes would share a slot; every entry's key is compared with its tile
+// group's first key (k_tile_insert) and every run's key with its lattice
+// point's stored key (k_tile_order), and the host rebuilds with a new seed
+// if any differ, so the final lattice is exact.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -49,8 +55,28 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long h) {
   return h;
 }
 
-__device__ __forceinline__ unsigned long long hash_step(unsigned long long h, int32_t v) {
-  return mix64(h ^ (unsigned long long)(uint32_t)v) + 0x9e3779b97f4a7c15ull;
+// Key hash: a seeded linear form sum_l a_l v_l (mod 2^64) over the stored
+// coordinates with odd coefficients a_l, then a 64-bit mix (a bijection) so
+// that the low bits index the table. One 64-bit multiply per coordinate.
+struct HashCoef {
+  unsigned long long a[kMaxD];
+};
+
+inline HashCoef hash_coef(unsigned long long seed) {
+  HashCoef c;
+  unsigned long long x = seed;
+  for (int l = 0; l < kMaxD; ++l) {
+    x += 0x9e3779b97f4a7c15ull;  // splitmix64 sequence
+    unsigned long long z = x;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    c.a[l] = (z ^ (z >> 31)) | 1ull;
+  }
+  return c;
+}
+
+__device__ __forceinline__ unsigned long long hash_acc(unsigned long long h, unsigned long long a, int32_t v) {
+  return h + a * (unsigned long long)(long long)v;
 }
 
 __device__ __forceinline__ unsigned long long hash_final(unsigned long long h) {
@@ -66,11 +92,6 @@ struct SimplexArgs {
   float* w;
   int32_t* pt_r0;
   uint8_t* pt_rank;
-  int32_t* slot;
-  unsigned long long* tab;
-  uint32_t* tab_first;
-  unsigned long long mask;
-  unsigned long long seed;
   uint32_t* flags;
   int32_t* rmin;  // per-dimension min / max of the remainder-0 point, in units of d+1
   int32_t* rmax;
@@ -109,125 +130,108 @@ __device__ int64_t table_find(const unsigned long long* tab, unsigned long long 
 // elevated point and, later, vertex j of its simplex. Values other lanes
 // need pass through LDS between barriers. Each floating-point operation
 // rounds once (no contraction), so keys and weights are reproducible.
-__global__ __launch_bounds__(kBlock) void k_simplex_insert(SimplexArgs a) {
+// Blocks take groups of P points in turn; the per-dimension range of the
+// remainder-0 points is gathered in LDS and merged into the global words
+// once per block (one block per group would put millions of atomics on the
+// same few words).
+constexpr int kElevateBlocks = 1024;
+__global__ __launch_bounds__(kBlock) void k_elevate(SimplexArgs a) {
   __shared__ double sh_a[kBlock];    // scaled inputs c_j, then residuals
   __shared__ double sh_q[kBlock];    // residuals / (d+1) in rank order
-  __shared__ int32_t sh_i[kBlock];   // quotients, then remainder-0 coordinates
-  __shared__ int32_t sh_rk[kBlock];  // ranks after the sum fix
+  __shared__ int32_t sh_i[kBlock];   // quotients
   __shared__ int32_t sh_bad[kBlock];
+  __shared__ int32_t sh_min[kMaxD], sh_max[kMaxD];
   const int d = a.d, D = d + 1;
   const int P = kBlock / D;
   const int tid = threadIdx.x;
   const int p = tid / D, j = tid - p * D;
-  const int64_t i = (int64_t)blockIdx.x * P + p;
-  const bool live = (p < P) && (i < a.n);
   const int base = p * D;
-
-  sh_bad[tid] = 0;
-  double cj = 0.0;
-  if (live && j >= 1) cj = (double)a.X[i * d + (j - 1)] * a.f[j - 1];
-  sh_a[tid] = cj;
-  __syncthreads();
-
-  // elevation: y_j = (c_d + c_{d-1} + ... + c_{j+1}) - j c_j, and y_0 = sum of all c
-  double y = 0.0;
-  if (live) {
-    double S = 0.0;
-    for (int l = d; l > j; --l) S = S + sh_a[base + l];
-    y = (j >= 1) ? S - (double)j * cj : S;
-  }
-  uint32_t bad = 0;
-  int32_t q = 0;
-  if (live) {
-    if (isnan(y) || isinf(y)) bad = BF_NONFINITE;
-    else if (!(fabs(y) <= kKeyLimit)) bad = BF_OVERFLOW;
-    else q = (int32_t)rint(y / (double)D);  // nearest multiple of d+1 (ties to even)
-  }
-  sh_i[tid] = q;
-  if (bad) {
-    sh_bad[base] = 1;
-    atomicOr(a.flags, bad);
-  }
-  __syncthreads();
-  const bool ok = live && sh_bad[base] == 0;
-
-  int32_t r0 = q * D;
-  int dsum = 0;
-  if (ok)
-    for (int l = 0; l < D; ++l) dsum += sh_i[base + l];
-  double del = y - (double)r0;
-  sh_a[tid] = del;
-  __syncthreads();
-
-  // rank 0 = largest residual; equal residuals rank the lower index first
-  int rank = 0;
-  if (ok) {
-    for (int l = 0; l < D; ++l) {
-      const double o = sh_a[base + l];
-      rank += (o > del || (o == del && l < j)) ? 1 : 0;
-    }
-    // make the remainder-0 point sum to zero by moving |dsum| coordinates by d+1
-    if (dsum > 0) {
-      if (rank >= D - dsum) { r0 -= D; rank += dsum - D; }
-      else rank += dsum;
-    } else if (dsum < 0) {
-      if (rank < -dsum) { r0 += D; rank += dsum + D; }
-      else rank += dsum;
-    }
-  }
-  rank = min(max(rank, 0), d);
-  del = y - (double)r0;
-  if (ok) sh_q[base + rank] = del / (double)D;
-  sh_i[tid] = r0;
-  sh_rk[tid] = rank;
-  __shared__ int32_t sh_min[kMaxD], sh_max[kMaxD];
   if (tid < d) {
     sh_min[tid] = INT32_MAX;
     sh_max[tid] = INT32_MIN;
   }
-  __syncthreads();
-  if (ok && j < d) {
-    atomicMin(&sh_min[j], r0 / D);
-    atomicMax(&sh_max[j], r0 / D);
+  const int64_t groups = (a.n + P - 1) / P;
+  for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    const int64_t i = g * P + p;
+    const bool live = (p < P) && (i < a.n);
+    sh_bad[tid] = 0;
+    double cj = 0.0;
+    if (live && j >= 1) cj = (double)a.X[i * d + (j - 1)] * a.f[j - 1];
+    sh_a[tid] = cj;
+    __syncthreads();
+
+    // elevation: y_j = (c_d + c_{d-1} + ... + c_{j+1}) - j c_j, and y_0 = sum of all c
+    double y = 0.0;
+    if (live) {
+      double S = 0.0;
+      for (int l = d; l > j; --l) S = S + sh_a[base + l];
+      y = (j >= 1) ? S - (double)j * cj : S;
+    }
+    uint32_t bad = 0;
+    int32_t q = 0;
+    if (live) {
+      if (isnan(y) || isinf(y)) bad = BF_NONFINITE;
+      else if (!(fabs(y) <= kKeyLimit)) bad = BF_OVERFLOW;
+      else q = (int32_t)rint(y / (double)D);  // nearest multiple of d+1 (ties to even)
+    }
+    sh_i[tid] = q;
+    if (bad) {
+      sh_bad[base] = 1;
+      atomicOr(a.flags, bad);
+    }
+    __syncthreads();
+    const bool ok = live && sh_bad[base] == 0;
+
+    int32_t r0 = q * D;
+    int dsum = 0;
+    if (ok)
+      for (int l = 0; l < D; ++l) dsum += sh_i[base + l];
+    double del = y - (double)r0;
+    sh_a[tid] = del;
+    __syncthreads();
+
+    // rank 0 = largest residual; equal residuals rank the lower index first
+    int rank = 0;
+    if (ok) {
+      for (int l = 0; l < D; ++l) {
+        const double o = sh_a[base + l];
+        rank += (o > del || (o == del && l < j)) ? 1 : 0;
+      }
+      // make the remainder-0 point sum to zero by moving |dsum| coordinates by d+1
+      if (dsum > 0) {
+        if (rank >= D - dsum) { r0 -= D; rank += dsum - D; }
+        else rank += dsum;
+      } else if (dsum < 0) {
+        if (rank < -dsum) { r0 += D; rank += dsum + D; }
+        else rank += dsum;
+      }
+    }
+    rank = min(max(rank, 0), d);
+    del = y - (double)r0;
+    if (ok) sh_q[base + rank] = del / (double)D;
+    if (ok && j < d) {
+      atomicMin(&sh_min[j], r0 / D);
+      atomicMax(&sh_max[j], r0 / D);
+    }
+    __syncthreads();
+    if (ok) {  // a rejected point fails the build
+      // barycentric weight of vertex k (= this lane): gap between consecutive
+      // sorted residuals; vertex 0 takes the remainder
+      const int k = j;
+      const double b = (k >= 1) ? sh_q[base + d - k] - sh_q[base + d + 1 - k]
+                                : sh_q[base + d] + (1.0 - sh_q[base]);
+      a.w[i * D + k] = (float)b;
+      if (j < d) {
+        a.pt_r0[i * d + j] = r0;
+        a.pt_rank[i * d + j] = (uint8_t)rank;
+      }
+    }
   }
   __syncthreads();
   if (tid < d && sh_min[tid] <= sh_max[tid]) {
     atomicMin(&a.rmin[tid], sh_min[tid]);
     atomicMax(&a.rmax[tid], sh_max[tid]);
   }
-  if (!ok) {
-    if (live) a.slot[i * D + j] = -1;  // rejected point: later passes skip its vertices
-    return;
-  }
-
-  // barycentric weight of vertex k (= this lane): gap between consecutive
-  // sorted residuals; vertex 0 takes the remainder
-  const int k = j;
-  const double b = (k >= 1) ? sh_q[base + d - k] - sh_q[base + d + 1 - k]
-                            : sh_q[base + d] + (1.0 - sh_q[base]);
-  const int64_t e = i * D + k;
-  a.w[e] = (float)b;
-  if (j < d) {
-    a.pt_r0[i * d + j] = r0;
-    a.pt_rank[i * d + j] = (uint8_t)rank;
-  }
-  // vertex k = r0 + canonical vertex s_k permuted by rank (eq. canon_simplex)
-  unsigned long long h = a.seed;
-  for (int l = 0; l < d; ++l) {
-    const int32_t v = sh_i[base + l] + k - (sh_rk[base + l] > d - k ? D : 0);
-    h = hash_step(h, v);
-  }
-  h = hash_final(h);
-  const int64_t s = table_insert(a.tab, a.mask, h);
-  if (s < 0) {
-    atomicOr(a.flags, BF_TABLE_FULL);
-    a.slot[e] = -1;
-    return;
-  }
-  const uint32_t ue = (uint32_t)e;
-  if (__hip_atomic_load(&a.tab_first[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > ue)
-    atomicMin(&a.tab_first[s], ue);
-  a.slot[e] = (int32_t)s;
 }
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
@@ -329,33 +333,6 @@ __global__ __launch_bounds__(kBlock) void k_compact(const int32_t* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_resolve(const int32_t* __restrict__ slot,
-                                                    const uint32_t* __restrict__ tab_first, int64_t L,
-                                                    const int32_t* __restrict__ pt_r0,
-                                                    const uint8_t* __restrict__ pt_rank, int d,
-                                                    const int32_t* __restrict__ keys, int64_t m,
-                                                    int32_t* __restrict__ idx,
-                                                    uint32_t* __restrict__ flags) {
-  const int D = d + 1;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += stride) {
-    const int32_t s = slot[e];
-    const uint32_t v = s >= 0 ? tab_first[s] : 0u;
-    if (!(v & kCanonBit) || (int64_t)(v & ~kCanonBit) >= m) {
-      idx[e] = 0;
-      atomicOr(flags, BF_COLLISION);
-      continue;
-    }
-    const int32_t j = (int32_t)(v & ~kCanonBit);
-    idx[e] = j;
-    const int64_t i = e / D;
-    const int k = (int)(e - i * D);
-    bool same = true;
-    for (int l = 0; l < d; ++l) same &= keys[(int64_t)j * d + l] == vertex_coord(pt_r0, pt_rank, i, d, k, l);
-    if (!same) atomicOr(flags, BF_COLLISION);
-  }
-}
-
 // Neighbour of lattice point j along direction k at offset t is
 // key + t (1 - (d+1) e_k): +t on every stored coordinate except -t d on
 // coordinate k (for k = d, +t on all of them). Thread g covers (k, j) with
@@ -365,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict_
                                                       const unsigned long long* __restrict__ tab,
                                                       const uint32_t* __restrict__ tab_first,
                                                       unsigned long long mask,
-                                                      unsigned long long seed,
+                                                      HashCoef hc,
                                                       int32_t* __restrict__ nbr) {
   const int D = d + 1, T = 2 * r;
   const int64_t total = m * D;
@@ -377,8 +354,8 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict_
     int ti = 0;
     for (int t = -r; t <= r; ++t) {
       if (t == 0) continue;
-      unsigned long long h = seed;
-      for (int l = 0; l < d; ++l) h = hash_step(h, kj[l] + (l == k ? -t * d : t));
+      unsigned long long h = 0;
+      for (int l = 0; l < d; ++l) h = hash_acc(h, hc.a[l], kj[l] + (l == k ? -t * d : t));
       h = hash_final(h);
       int32_t found = -1;
       const int64_t s = table_find(tab, mask, h);
@@ -422,22 +399,6 @@ __global__ __launch_bounds__(kBlock) void k_point_key(const int32_t* __restrict_
       k |= (unsigned long long)(uint32_t)(pt_r0[i * d + l] / D - kp.lo[l]) << kp.shift[l];
     key[i] = k;
     val[i] = (uint32_t)i;
-  }
-}
-
-// Slot of every (sorted point, vertex) element and first touch per slot.
-__global__ __launch_bounds__(kBlock) void k_first_touch(const uint32_t* __restrict__ perm,
-                                                        const int32_t* __restrict__ slot, int64_t L,
-                                                        int D, int32_t* __restrict__ slot_s,
-                                                        uint32_t* __restrict__ first2) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += stride) {
-    const int64_t ip = e / D;
-    const int k = (int)(e - ip * D);
-    const int32_t s = slot[(int64_t)perm[ip] * D + k];
-    slot_s[e] = s;
-    if (__hip_atomic_load(&first2[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (uint32_t)e)
-      atomicMin(&first2[s], (uint32_t)e);
   }
 }
 
@@ -523,9 +484,9 @@ __global__ __launch_bounds__(kBlock) void k_nbr_internal(const int32_t* __restri
 // (internal lattice point, entry): equal lattice points form a "run" (one
 // lattice point of one tile, its entries in sorted-point order), and runs are
 // cut into pieces of at most K entries for the splat. A tile holds at most
-// kTileSlots entries, so one block sorts it in LDS (bitonic network over the
-// unique keys (lattice point << 12) | entry), which gives the same order as a
-// stable sort of all entries by (tile, lattice point).
+// kTileSlots entries, so one block sorts it in LDS (a stable radix sort of
+// the keys (lattice point << 12) | entry by lattice point), which gives the
+// same order as a stable sort of all entries by (tile, lattice point).
 constexpr int kTileThreads = 1024;
 constexpr int kTileSlots = 4096;
 constexpr int kTileSpan = kTileSlots / kTileThreads;  // consecutive slots per thread
@@ -534,6 +495,7 @@ struct TileSort {
   unsigned long long key[kTileSlots];
   int32_t rstart[kTileSlots];  // sorted position of each run's first entry
   int32_t wsum[kTileThreads / 64];
+  unsigned long long wsum64[kTileThreads / 64];
 };
 
 // Block-wide exclusive scan of one count per thread; *total gets the sum.
@@ -557,21 +519,61 @@ __device__ inline int tile_scan(int v, int32_t* wsum, int* total) {
   return before + x - v;
 }
 
-// Sort the N (a power of two) keys ascending.
-__device__ inline void tile_bitonic(unsigned long long* key, int N) {
-  for (int k = 2; k <= N; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < N / 2; i += kTileThreads) {
-        const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-        const int hi = lo + j;
-        const unsigned long long x = key[lo], y = key[hi];
-        if ((x > y) == ((lo & k) == 0)) {
-          key[lo] = y;
-          key[hi] = x;
-        }
-      }
-      __syncthreads();
+// Block-wide exclusive scan of one 64-bit value per thread (packed
+// counters that do not carry into each other); *total gets the sum.
+__device__ inline unsigned long long tile_scan64(unsigned long long v, unsigned long long* wsum,
+                                                 unsigned long long* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned long long x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  unsigned long long before = 0, all = 0;
+  for (int i = 0; i < kTileThreads / 64; ++i) {
+    const unsigned long long c = wsum[i];
+    before += i < w ? c : 0;
+    all += c;
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+// Stable LSD radix sort of all kTileSlots keys by their lattice-point field
+// (key >> 12; entries past the tile hold ~0 and stay last), two bits per
+// pass. The four bucket counts of a thread's keys travel as 13-bit fields
+// of one 64-bit word through one block scan. key[] holds the keys in entry
+// order on entry and sorted on exit.
+__device__ inline void tile_radix(unsigned long long* key, unsigned long long* wsum, int bits) {
+  const int i0 = threadIdx.x * kTileSpan;
+  unsigned long long v[kTileSpan];
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) v[u] = key[i0 + u];
+  for (int b = 0; b < bits; b += 2) {
+    int dg[kTileSpan];
+    unsigned long long cnt = 0;
+#pragma unroll
+    for (int u = 0; u < kTileSpan; ++u) {
+      dg[u] = (int)((v[u] >> (12 + b)) & 3u);
+      cnt += 1ull << (13 * dg[u]);
     }
+    unsigned long long tot;
+    unsigned long long run = tile_scan64(cnt, wsum, &tot);
+    const int t0 = (int)(tot & 8191u), t1 = (int)((tot >> 13) & 8191u), t2 = (int)((tot >> 26) & 8191u);
+    const int bucket0[4] = {0, t0, t0 + t1, t0 + t1 + t2};
+#pragma unroll
+    for (int u = 0; u < kTileSpan; ++u) {
+      const int pos = bucket0[dg[u]] + (int)((run >> (13 * dg[u])) & 8191u);
+      run += 1ull << (13 * dg[u]);
+      key[pos] = v[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kTileSpan; ++u) v[u] = key[i0 + u];
+    __syncthreads();
   }
 }
 
@@ -618,24 +620,43 @@ __device__ inline void tile_ranks(TileSort& T, int ne, int K, TileRanks& r) {
 
 // Pass 1: sort each tile, keep the order (entry within the tile per sorted
 // position) and count its runs and pieces.
+// Each run's key is also compared with its lattice point's canonical key:
+// distinct keys with equal hashes in different tiles share a lattice point,
+// and one of their runs then differs from it.
 __global__ __launch_bounds__(kTileThreads) void k_tile_order(const sgp_entry* __restrict__ pm, int64_t n,
-                                                             int D, int P, int K,
+                                                             int D, int P, int K, int mbits,
+                                                             const uint32_t* __restrict__ perm,
+                                                             const int32_t* __restrict__ pt_r0,
+                                                             const uint8_t* __restrict__ pt_rank,
+                                                             const int32_t* __restrict__ keys,
+                                                             const int32_t* __restrict__ int2can,
                                                              uint16_t* __restrict__ ord,
                                                              uint32_t* __restrict__ runs,
-                                                             uint32_t* __restrict__ pieces) {
+                                                             uint32_t* __restrict__ pieces,
+                                                             uint32_t* __restrict__ flags) {
   __shared__ TileSort T;
   const int64_t t = blockIdx.x;
   const int64_t p0 = t * P;
   const int ne = (int)((n - p0 < P ? n - p0 : P) * D);
   const int64_t base = p0 * D;
-  int N = 64;
-  while (N < ne) N <<= 1;
-  for (int i = threadIdx.x; i < N; i += kTileThreads)
+  for (int i = threadIdx.x; i < kTileSlots; i += kTileThreads)
     T.key[i] = i < ne ? ((unsigned long long)(uint32_t)pm[base + i].j << 12) | (unsigned)i : ~0ull;
   __syncthreads();
-  tile_bitonic(T.key, N);
+  tile_radix(T.key, T.wsum64, mbits);
   TileRanks r;
   tile_ranks(T, ne, K, r);
+  // one thread per run: its first entry's key against the stored key
+  const int d = D - 1;
+  bool bad = false;
+  for (int q = threadIdx.x; q < r.runs; q += kTileThreads) {
+    const unsigned long long k = T.key[T.rstart[q]];
+    const unsigned le = (unsigned)(k & 4095u);
+    const int64_t pt = perm[p0 + le / (unsigned)D];
+    const int kv = (int)(le % (unsigned)D);
+    const int32_t* key = keys + (int64_t)int2can[k >> 12] * d;
+    for (int l = 0; l < d; ++l) bad |= key[l] != vertex_coord(pt_r0, pt_rank, pt, d, kv, l);
+  }
+  if (bad) atomicOr(flags, BF_COLLISION);
   for (int i = threadIdx.x; i < ne; i += kTileThreads) ord[base + i] = (uint16_t)(T.key[i] & 4095u);
   if (threadIdx.x == 0) {
     runs[t] = (uint32_t)r.runs;
@@ -688,6 +709,153 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_fill(const sgp_entry* __r
     if (r.qp[u] >= 0) {
       run_rel[qp0 + r.qp[u]] = (uint16_t)i;
       piece_vert[qp0 + r.qp[u]] = j;
+    }
+  }
+}
+
+// Hashing and first occurrences, one group of kInsEntries / (d+1)
+// consecutive sorted points per block. Its entries (simplex vertices) are
+// hashed from the staged remainder-0 coordinates and ranks and grouped by
+// hash in an LDS table whose slot keeps the group's smallest entry (its
+// representative). The group is smaller than a tile, so that several blocks
+// share a CU and hide each other's latencies. Each group is inserted
+// into the global table once; per global slot the smallest caller-order
+// entry (canonical numbering) and the smallest sorted-order entry (first
+// touch) are kept with one atomic each per (tile, slot). Every entry's key
+// must equal its representative's; one that differs is a hash collision.
+constexpr int kInsThreads = 256;
+constexpr int kInsSpan = 4;                          // consecutive entries per thread
+constexpr int kInsEntries = kInsThreads * kInsSpan;  // entries per block, at most
+constexpr int kInsTable = 2 * kInsEntries;           // LDS table slots (load factor <= 1/2)
+constexpr uint32_t kLdsEmpty = 0xffffffffu;
+struct TileInsertLds {
+  unsigned long long h[kInsEntries];  // entry hashes; then (global slot, min caller entry) per representative
+  uint32_t table[kInsTable];          // representative of the group in each slot
+  int32_t r0[kInsEntries];            // the points' remainder-0 coordinates (points * d < kInsEntries)
+  uint8_t rk[kInsEntries];            // and their ranks
+  uint32_t op[kInsEntries / 2];       // caller index of each point
+};
+
+__device__ __forceinline__ int32_t staged_coord(const TileInsertLds& S, int lp, int d, int k, int l) {
+  return S.r0[lp * d + l] + k - ((int)S.rk[lp * d + l] > d - k ? d + 1 : 0);
+}
+
+// Global slot of hash h: claimed by compare-and-swap if empty; -1 if full.
+__device__ int64_t table_claim(unsigned long long* tab, unsigned long long mask, unsigned long long h) {
+  unsigned long long s = h & mask;
+  for (unsigned long long probe = 0; probe <= mask; ++probe) {
+    const unsigned long long prev = atomicCAS(&tab[s], kEmpty, h);
+    if (prev == kEmpty || prev == h) return (int64_t)s;
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(kInsThreads) void k_tile_insert(
+    const uint32_t* __restrict__ perm, const int32_t* __restrict__ pt_r0,
+    const uint8_t* __restrict__ pt_rank, int64_t n, int d, int P, unsigned long long* __restrict__ tab,
+    uint32_t* __restrict__ tab_first, uint32_t* __restrict__ first2, unsigned long long mask,
+    HashCoef hc, int32_t* __restrict__ slot, int32_t* __restrict__ slot_s,
+    uint32_t* __restrict__ flags) {
+  __shared__ TileInsertLds S;
+  const int D = d + 1;
+  const int64_t t = blockIdx.x;
+  const int64_t p0 = t * P;
+  const int np = (int)(n - p0 < P ? n - p0 : P);
+  const int ne = np * D;
+  const int64_t base = p0 * D;
+  for (int lp = threadIdx.x; lp < np; lp += kInsThreads) S.op[lp] = perm[p0 + lp];
+  for (int q = threadIdx.x; q < kInsTable; q += kInsThreads) S.table[q] = kLdsEmpty;
+  __syncthreads();
+  for (int q = threadIdx.x; q < np * d; q += kInsThreads) {
+    const int lp = q / d, l = q - lp * d;
+    const int64_t src = (int64_t)S.op[lp] * d + l;
+    S.r0[q] = pt_r0[src];
+    S.rk[q] = pt_rank[src];
+  }
+  __syncthreads();
+  // thread tid owns entries e0 .. e0 + kInsSpan - 1
+  const int e0 = threadIdx.x * kInsSpan;
+  unsigned long long hv[kInsSpan];
+#pragma unroll
+  for (int u = 0; u < kInsSpan; ++u) {
+    const int e = e0 + u;
+    hv[u] = 0;
+    if (e < ne) {
+      const int lp = e / D, k = e - lp * D;
+      unsigned long long h = 0;
+      for (int l = 0; l < d; ++l) h = hash_acc(h, hc.a[l], staged_coord(S, lp, d, k, l));
+      hv[u] = hash_final(h);
+      S.h[e] = hv[u];
+    }
+  }
+  __syncthreads();
+  // group by hash: the first probe slot holding this hash, or an empty one
+  // claimed; the slot then keeps the smallest entry of its group
+  int ts[kInsSpan];
+#pragma unroll
+  for (int u = 0; u < kInsSpan; ++u) {
+    const int e = e0 + u;
+    ts[u] = -1;
+    if (e >= ne) continue;
+    int s = (int)(hv[u] & (kInsTable - 1));
+    for (int probe = 0; probe < kInsTable; ++probe) {
+      uint32_t cur = S.table[s];
+      if (cur == kLdsEmpty) {
+        cur = atomicCAS(&S.table[s], kLdsEmpty, (uint32_t)e);
+        if (cur == kLdsEmpty) {
+          ts[u] = s;
+          break;
+        }
+      }
+      if (S.h[cur] == hv[u]) {
+        atomicMin(&S.table[s], (uint32_t)e);
+        ts[u] = s;
+        break;
+      }
+      s = (s + 1) & (kInsTable - 1);
+    }
+  }
+  __syncthreads();
+  int rep[kInsSpan];
+#pragma unroll
+  for (int u = 0; u < kInsSpan; ++u) rep[u] = ts[u] >= 0 ? (int)S.table[ts[u]] : -1;
+  __syncthreads();  // the hashes are no longer read: representatives take (slot, min caller entry)
+  uint32_t* g32 = reinterpret_cast<uint32_t*>(S.h);
+#pragma unroll
+  for (int u = 0; u < kInsSpan; ++u) {
+    const int e = e0 + u;
+    if (rep[u] != e) continue;
+    const int64_t sl = table_claim(tab, mask, hv[u]);
+    if (sl < 0) atomicOr(flags, BF_TABLE_FULL);
+    g32[2 * e] = (uint32_t)sl;
+    g32[2 * e + 1] = 0xffffffffu;
+  }
+  __syncthreads();
+  bool bad = false;
+  uint32_t eo[kInsSpan];
+#pragma unroll
+  for (int u = 0; u < kInsSpan; ++u) {
+    const int e = e0 + u;
+    if (rep[u] < 0) continue;
+    const int lp = e / D, k = e - lp * D;
+    eo[u] = S.op[lp] * (uint32_t)D + (uint32_t)k;  // caller-order entry
+    atomicMin(&g32[2 * rep[u] + 1], eo[u]);
+    const int rlp = rep[u] / D, rk = rep[u] - rlp * D;
+    for (int l = 0; l < d; ++l) bad |= staged_coord(S, lp, d, k, l) != staged_coord(S, rlp, d, rk, l);
+  }
+  if (bad) atomicOr(flags, BF_COLLISION);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kInsSpan; ++u) {
+    const int e = e0 + u;
+    if (rep[u] < 0) continue;
+    const int32_t sl = (int32_t)g32[2 * rep[u]];
+    slot_s[base + e] = sl;
+    slot[eo[u]] = sl;
+    if (rep[u] == e && sl >= 0) {
+      atomicMin(&tab_first[sl], g32[2 * e + 1]);
+      atomicMin(&first2[sl], (uint32_t)(base + e));
     }
   }
 }
@@ -779,12 +947,13 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     return SGP_EINVAL;
   }
   const int64_t nb = (Lel + kChunk - 1) / kChunk;
+  const HashCoef hc = hash_coef(seed);
 
   Transient tr;
   tr.s = st;
   int rc;
   enum {
-    T_R0, T_RANK, T_SLOT, T_TAB, T_FIRST, T_COUNTS, T_OFFS, T_WORDS, T_IDX, T_W, T_NBRC,
+    T_R0, T_RANK, T_SLOT, T_TAB, T_FIRST, T_COUNTS, T_OFFS, T_WORDS, T_W, T_NBRC,
     T_SLOTS, T_FIRST2, T_CAN2INT, T_KA, T_KB, T_VA, T_VB, T_SORTTMP, T_PM, T_SUB, T_ORD, T_CNT
   };
   if ((rc = tr.alloc(T_R0, sizeof(int32_t) * n * d))) return rc;
@@ -795,7 +964,6 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   if ((rc = tr.alloc(T_COUNTS, sizeof(uint32_t) * nb))) return rc;
   if ((rc = tr.alloc(T_OFFS, sizeof(uint32_t) * nb))) return rc;
   if ((rc = tr.alloc(T_WORDS, sizeof(uint32_t) * (4 + 2 * kMaxD)))) return rc;
-  if ((rc = tr.alloc(T_IDX, sizeof(int32_t) * Lel))) return rc;
   if ((rc = tr.alloc(T_W, sizeof(float) * Lel))) return rc;
   int32_t* pt_r0 = (int32_t*)tr.ptr[T_R0];
   uint8_t* pt_rank = (uint8_t*)tr.ptr[T_RANK];
@@ -805,13 +973,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   uint32_t* counts = (uint32_t*)tr.ptr[T_COUNTS];
   uint32_t* offs = (uint32_t*)tr.ptr[T_OFFS];
   uint32_t* words = (uint32_t*)tr.ptr[T_WORDS];  // [0] flags, [1] m, [2] m again, [4..] min/max
-  int32_t* idx_orig = (int32_t*)tr.ptr[T_IDX];
   float* w_orig = (float*)tr.ptr[T_W];
   int32_t* rmin = (int32_t*)(words + 4);
   int32_t* rmax = rmin + kMaxD;
 
-  if ((rc = launch_fill_u32((uint32_t*)tab, (size_t)cap * 2, 0u, st))) return rc;
-  if ((rc = launch_fill_u32(tab_first, (size_t)cap, kNoFirst, st))) return rc;
   if ((rc = launch_fill_u32(words, 4, 0u, st))) return rc;
   if ((rc = launch_fill_u32((uint32_t*)rmin, kMaxD, 0x7fffffffu, st))) return rc;
   if ((rc = launch_fill_u32((uint32_t*)rmax, kMaxD, 0x80000000u, st))) return rc;
@@ -824,51 +989,24 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   a.w = w_orig;
   a.pt_r0 = pt_r0;
   a.pt_rank = pt_rank;
-  a.slot = slot;
-  a.tab = tab;
-  a.tab_first = tab_first;
-  a.mask = (unsigned long long)(cap - 1);
-  a.seed = seed;
   a.flags = words;
   a.rmin = rmin;
   a.rmax = rmax;
-  const int P = kBlock / D;
   {
     ProfScope ps(KK_SIMPLEX, st);
-    hipLaunchKernelGGL(k_simplex_insert, dim3(grid_for(n, P, INT32_MAX)), dim3(kBlock), 0, st, a);
-    SGP_LAUNCH_CHECK("k_simplex_insert");
-  }
-  {
-    ProfScope ps(KK_COUNT, st);
-    hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel,
-                       counts);
-    SGP_LAUNCH_CHECK("k_count_first");
-  }
-  {
-    ProfScope ps(KK_SCAN, st);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, counts, offs, nb, words + 1);
-    SGP_LAUNCH_CHECK("k_scan");
+    hipLaunchKernelGGL(k_elevate, dim3(grid_for(n, kBlock / D, kElevateBlocks)), dim3(kBlock), 0, st, a);
+    SGP_LAUNCH_CHECK("k_elevate");
   }
   const size_t nwords = 4 + 2 * kMaxD;
   SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * nwords, hipMemcpyDeviceToHost, st));
   SGP_HIP(hipStreamSynchronize(st));
-  const uint32_t flags = host_word[0];
-  const int64_t m = host_word[1];
-  if (flags & BF_NONFINITE) {
+  if (host_word[0] & BF_NONFINITE) {
     set_error("lattice_build: X contains NaN or Inf");
     return SGP_EINVAL;
   }
-  if (flags & BF_OVERFLOW) {
+  if (host_word[0] & BF_OVERFLOW) {
     set_error("lattice_build: |x|/lengthscale too large, a lattice coordinate leaves int32");
     return SGP_EOVERFLOW;
-  }
-  if (flags & BF_TABLE_FULL) {
-    set_error("lattice_build: hash table full");
-    return SGP_EHASH;
-  }
-  if (m < 1 || m > Lel) {
-    set_error("lattice_build: inconsistent lattice size %lld", (long long)m);
-    return SGP_EHASH;
   }
   // sort key: remainder-0 coordinates, leading dimensions first, as many as fit in 64 bits
   KeyPack kp;
@@ -893,36 +1031,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     kp.nk = nk;
     key_bits = used;
   }
-  L->m = m;
-  dev_free(L->keys);
-  if ((rc = dev_alloc(L->keys, sizeof(int32_t) * m * d, st))) return rc;
-  if ((rc = tr.alloc(T_NBRC, sizeof(int32_t) * m * D * T))) return rc;
-  int32_t* nbr_can = (int32_t*)tr.ptr[T_NBRC];
-  {
-    ProfScope ps(KK_COMPACT, st);
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel, offs,
-                       pt_r0, pt_rank, d, m, (int32_t*)L->keys.ptr, words);
-    SGP_LAUNCH_CHECK("k_compact");
-  }
-  {
-    ProfScope ps(KK_RESOLVE, st);
-    hipLaunchKernelGGL(k_resolve, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, slot,
-                       tab_first, Lel, pt_r0, pt_rank, d, (const int32_t*)L->keys.ptr, m,
-                       idx_orig, words);
-    SGP_LAUNCH_CHECK("k_resolve");
-  }
-  {
-    ProfScope ps(KK_NEIGHBORS, st);
-    hipLaunchKernelGGL(k_neighbors, dim3(grid_for(m * D, kBlock, 16384)), dim3(kBlock), 0, st,
-                       (const int32_t*)L->keys.ptr, m, d, L->order, tab, tab_first,
-                       (unsigned long long)(cap - 1), seed, nbr_can);
-    SGP_LAUNCH_CHECK("k_neighbors");
-  }
 
   // ---- internal order: sort points, renumber vertices by first touch
   if ((rc = tr.alloc(T_SLOTS, sizeof(int32_t) * Lel))) return rc;
   if ((rc = tr.alloc(T_FIRST2, sizeof(uint32_t) * cap))) return rc;
-  if ((rc = tr.alloc(T_CAN2INT, sizeof(int32_t) * m))) return rc;
   // sort buffers: 64-bit point keys (n), then 32-bit piece keys (at most Lel)
   const size_t kbytes = std::max(sizeof(unsigned long long) * n, sizeof(uint32_t) * Lel);
   if ((rc = tr.alloc(T_KA, kbytes))) return rc;
@@ -933,7 +1045,6 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   if ((rc = tr.alloc(T_SORTTMP, sizeof(uint32_t) * radix_tmp_words(Lel)))) return rc;
   int32_t* slot_s = (int32_t*)tr.ptr[T_SLOTS];
   uint32_t* first2 = (uint32_t*)tr.ptr[T_FIRST2];
-  int32_t* can2int = (int32_t*)tr.ptr[T_CAN2INT];
   uint32_t* va = (uint32_t*)tr.ptr[T_VA];
   uint32_t* vb = (uint32_t*)tr.ptr[T_VB];
   uint32_t* sort_tmp = (uint32_t*)tr.ptr[T_SORTTMP];
@@ -944,8 +1055,6 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   // two spare slots: the slice reads slots in aligned pairs
   if ((rc = dev_alloc(L->loc, sizeof(uint16_t) * (Lel + 2), st))) return rc;
   if ((rc = dev_alloc(L->ws, sizeof(float) * Lel, st))) return rc;
-  if ((rc = dev_alloc(L->nbr, sizeof(int32_t) * m * D * T, st))) return rc;
-  if ((rc = dev_alloc(L->int2can, sizeof(int32_t) * m, st))) return rc;
   sgp_entry* pm = (sgp_entry*)tr.ptr[T_PM];
   uint32_t* perm = (uint32_t*)L->perm.ptr;
   {
@@ -962,13 +1071,76 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
       return rc;
     SGP_HIP(hipMemcpyAsync(perm, in_alt ? vb : va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
   }
+  // ---- hash the simplex vertices tile by tile in sorted order: slots, and
+  // per slot the first entry in caller order and in sorted order
+  // tile size: at most 256 points (a point index fits 8 bits) and 4096
+  // entries (the tile kernels stage a tile's entries in LDS); a multiple of
+  // 4, so that every tile's entries start 4-byte aligned in the 8- and
+  // 16-bit arrays
+  const int P = std::min(256, 4096 / D) & ~3;
+  const int64_t ntiles = (n + P - 1) / P;
+  if ((rc = launch_fill_u32((uint32_t*)tab, (size_t)cap * 2, 0u, st))) return rc;
+  if ((rc = launch_fill_u32(tab_first, (size_t)cap, kNoFirst, st))) return rc;
   if ((rc = launch_fill_u32(first2, (size_t)cap, kNoFirst, st))) return rc;
   {
-    ProfScope ps(KK_ORDER, st);
-    hipLaunchKernelGGL(k_first_touch, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st, perm,
-                       slot, Lel, D, slot_s, first2);
-    SGP_LAUNCH_CHECK("k_first_touch");
+    ProfScope ps(KK_SIMPLEX, st);
+    const int Pi = kInsEntries / D;
+    hipLaunchKernelGGL(k_tile_insert, dim3((unsigned)((n + Pi - 1) / Pi)), dim3(kInsThreads), 0, st,
+                       (const uint32_t*)perm, (const int32_t*)pt_r0, (const uint8_t*)pt_rank, n, d, Pi, tab,
+                       tab_first, first2, (unsigned long long)(cap - 1), hc, slot, slot_s, words);
+    SGP_LAUNCH_CHECK("k_tile_insert");
   }
+  {
+    ProfScope ps(KK_COUNT, st);
+    hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel,
+                       counts);
+    SGP_LAUNCH_CHECK("k_count_first");
+  }
+  {
+    ProfScope ps(KK_SCAN, st);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, counts, offs, nb, words + 1);
+    SGP_LAUNCH_CHECK("k_scan");
+  }
+  SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, st));
+  SGP_HIP(hipStreamSynchronize(st));
+  const uint32_t flags = host_word[0];
+  const int64_t m = host_word[1];
+  if (flags & BF_TABLE_FULL) {
+    set_error("lattice_build: hash table full");
+    return SGP_EHASH;
+  }
+  if (flags & BF_COLLISION) {  // two keys share a 64-bit hash: try another seed
+    tr.idle = true;
+    *retry = true;
+    return SGP_OK;
+  }
+  if (m < 1 || m > Lel) {
+    set_error("lattice_build: inconsistent lattice size %lld", (long long)m);
+    return SGP_EHASH;
+  }
+  L->m = m;
+  dev_free(L->keys);
+  if ((rc = dev_alloc(L->keys, sizeof(int32_t) * m * d, st))) return rc;
+  if ((rc = dev_alloc(L->nbr, sizeof(int32_t) * m * D * T, st))) return rc;
+  if ((rc = dev_alloc(L->int2can, sizeof(int32_t) * m, st))) return rc;
+  if ((rc = tr.alloc(T_NBRC, sizeof(int32_t) * m * D * T))) return rc;
+  if ((rc = tr.alloc(T_CAN2INT, sizeof(int32_t) * m))) return rc;
+  int32_t* nbr_can = (int32_t*)tr.ptr[T_NBRC];
+  int32_t* can2int = (int32_t*)tr.ptr[T_CAN2INT];
+  {
+    ProfScope ps(KK_COMPACT, st);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel, offs,
+                       pt_r0, pt_rank, d, m, (int32_t*)L->keys.ptr, words);
+    SGP_LAUNCH_CHECK("k_compact");
+  }
+  {
+    ProfScope ps(KK_NEIGHBORS, st);
+    hipLaunchKernelGGL(k_neighbors, dim3(grid_for(m * D, kBlock, 16384)), dim3(kBlock), 0, st,
+                       (const int32_t*)L->keys.ptr, m, d, L->order, tab, tab_first,
+                       (unsigned long long)(cap - 1), hc, nbr_can);
+    SGP_LAUNCH_CHECK("k_neighbors");
+  }
+  // ---- internal numbering: lattice points by first touch in sorted order
   {
     ProfScope ps(KK_COUNT, st);
     hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, slot_s, first2, Lel,
@@ -998,13 +1170,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   }
   // ---- tiles of consecutive sorted points, their runs, and runs per lattice point
   {
-    // tile size: at most 256 points (a point index fits 8 bits) and 4096
-    // entries (the tile kernels stage a tile's entries in LDS); a multiple
-    // of 4, so that every tile's entries start 4-byte aligned in the 8- and
-    // 16-bit arrays
-    const int P = std::min(256, 4096 / D) & ~3;
     L->tile_points = P;
-    const int64_t ntiles = (n + P - 1) / P;
     L->ntiles = ntiles;
     const int mb = bits_for((uint64_t)(m - 1));
     if ((rc = tr.alloc(T_ORD, sizeof(uint16_t) * Lel))) return rc;
@@ -1019,7 +1185,9 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     {
       ProfScope ps(KK_ORDER, st);
       hipLaunchKernelGGL(k_tile_order, dim3((unsigned)ntiles), dim3(kTileThreads), 0, st,
-                         (const sgp_entry*)tr.ptr[T_PM], n, D, P, kPiece, ord, runs, pieces);
+                         (const sgp_entry*)tr.ptr[T_PM], n, D, P, kPiece, mb, (const uint32_t*)perm,
+                         (const int32_t*)pt_r0, (const uint8_t*)pt_rank, (const int32_t*)L->keys.ptr,
+                         (const int32_t*)L->int2can.ptr, ord, runs, pieces, words);
       SGP_LAUNCH_CHECK("k_tile_order");
     }
     // first run and first piece of every tile; the totals land in entry ntiles
