@@ -491,8 +491,13 @@ constexpr int kTileThreads = 1024;
 constexpr int kTileSlots = 4096;
 constexpr int kTileSpan = kTileSlots / kTileThreads;  // consecutive slots per thread
 
+// Thread t owns sorted positions 4t .. 4t+3; position i is kept at LDS
+// index tile_at(i), so that the positions lanes access together are
+// consecutive words (no bank conflicts).
+__device__ __forceinline__ int tile_at(int i) { return (i & (kTileSpan - 1)) * kTileThreads + (i >> 2); }
+
 struct TileSort {
-  unsigned long long key[kTileSlots];
+  unsigned long long key[kTileSlots];  // at tile_at(position)
   int32_t rstart[kTileSlots];  // sorted position of each run's first entry
   int32_t wsum[kTileThreads / 64];
   unsigned long long wsum64[kTileThreads / 64];
@@ -551,7 +556,7 @@ __device__ inline void tile_radix(unsigned long long* key, unsigned long long* w
   const int i0 = threadIdx.x * kTileSpan;
   unsigned long long v[kTileSpan];
 #pragma unroll
-  for (int u = 0; u < kTileSpan; ++u) v[u] = key[i0 + u];
+  for (int u = 0; u < kTileSpan; ++u) v[u] = key[tile_at(i0 + u)];
   for (int b = 0; b < bits; b += 2) {
     int dg[kTileSpan];
     unsigned long long cnt = 0;
@@ -568,11 +573,11 @@ __device__ inline void tile_radix(unsigned long long* key, unsigned long long* w
     for (int u = 0; u < kTileSpan; ++u) {
       const int pos = bucket0[dg[u]] + (int)((run >> (13 * dg[u])) & 8191u);
       run += 1ull << (13 * dg[u]);
-      key[pos] = v[u];
+      key[tile_at(pos)] = v[u];
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kTileSpan; ++u) v[u] = key[i0 + u];
+    for (int u = 0; u < kTileSpan; ++u) v[u] = key[tile_at(i0 + u)];
     __syncthreads();
   }
 }
@@ -591,7 +596,7 @@ __device__ inline void tile_ranks(TileSort& T, int ne, int K, TileRanks& r) {
 #pragma unroll
   for (int u = 0; u < kTileSpan; ++u) {
     const int i = i0 + u;
-    r.rs[u] = i < ne && (i == 0 || (T.key[i] >> 12) != (T.key[i - 1] >> 12));
+    r.rs[u] = i < ne && (i == 0 || (T.key[tile_at(i)] >> 12) != (T.key[tile_at(i - 1)] >> 12));
     c += r.rs[u] ? 1 : 0;
   }
   int q = tile_scan(c, T.wsum, &r.runs) - 1;
@@ -623,7 +628,7 @@ __device__ inline void tile_ranks(TileSort& T, int ne, int K, TileRanks& r) {
 // Each run's key is also compared with its lattice point's canonical key:
 // distinct keys with equal hashes in different tiles share a lattice point,
 // and one of their runs then differs from it.
-__global__ __launch_bounds__(kTileThreads) void k_tile_order(const sgp_entry* __restrict__ pm, int64_t n,
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_order(const sgp_entry* __restrict__ pm, int64_t n,
                                                              int D, int P, int K, int mbits,
                                                              const uint32_t* __restrict__ perm,
                                                              const int32_t* __restrict__ pt_r0,
@@ -639,8 +644,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(const sgp_entry* __
   const int64_t p0 = t * P;
   const int ne = (int)((n - p0 < P ? n - p0 : P) * D);
   const int64_t base = p0 * D;
-  for (int i = threadIdx.x; i < kTileSlots; i += kTileThreads)
-    T.key[i] = i < ne ? ((unsigned long long)(uint32_t)pm[base + i].j << 12) | (unsigned)i : ~0ull;
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    const int i = threadIdx.x * kTileSpan + u;
+    T.key[tile_at(i)] = i < ne ? ((unsigned long long)(uint32_t)pm[base + i].j << 12) | (unsigned)i : ~0ull;
+  }
   __syncthreads();
   tile_radix(T.key, T.wsum64, mbits);
   TileRanks r;
@@ -649,7 +657,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(const sgp_entry* __
   const int d = D - 1;
   bool bad = false;
   for (int q = threadIdx.x; q < r.runs; q += kTileThreads) {
-    const unsigned long long k = T.key[T.rstart[q]];
+    const unsigned long long k = T.key[tile_at(T.rstart[q])];
     const unsigned le = (unsigned)(k & 4095u);
     const int64_t pt = perm[p0 + le / (unsigned)D];
     const int kv = (int)(le % (unsigned)D);
@@ -657,7 +665,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(const sgp_entry* __
     for (int l = 0; l < d; ++l) bad |= key[l] != vertex_coord(pt_r0, pt_rank, pt, d, kv, l);
   }
   if (bad) atomicOr(flags, BF_COLLISION);
-  for (int i = threadIdx.x; i < ne; i += kTileThreads) ord[base + i] = (uint16_t)(T.key[i] & 4095u);
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    const int i = threadIdx.x * kTileSpan + u;
+    if (i < ne) ord[base + i] = (uint16_t)(T.key[tile_at(i)] & 4095u);
+  }
   if (threadIdx.x == 0) {
     runs[t] = (uint32_t)r.runs;
     pieces[t] = (uint32_t)r.pieces;
@@ -685,9 +697,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_fill(const sgp_entry* __r
   const int64_t p0 = t * P;
   const int ne = (int)((n - p0 < P ? n - p0 : P) * D);
   const int64_t base = p0 * D;
-  for (int i = threadIdx.x; i < ne; i += kTileThreads) {
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    const int i = threadIdx.x * kTileSpan + u;
+    if (i >= ne) break;
     const unsigned le = ord[base + i];
-    T.key[i] = ((unsigned long long)(uint32_t)pm[base + le].j << 12) | le;
+    T.key[tile_at(i)] = ((unsigned long long)(uint32_t)pm[base + le].j << 12) | le;
     ws[base + i] = pm[base + i].w;
   }
   __syncthreads();
@@ -699,7 +714,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_fill(const sgp_entry* __r
   for (int u = 0; u < kTileSpan; ++u) {
     const int i = i0 + u;
     if (i >= ne) break;
-    const unsigned long long k = T.key[i];
+    const unsigned long long k = T.key[tile_at(i)];
     const int32_t j = (int32_t)(k >> 12);
     const unsigned le = (unsigned)(k & 4095u);
     ent_lp[base + i] = (uint8_t)(le / (unsigned)D);
