@@ -170,6 +170,14 @@ const char* sgp_last_error(void);
  * Returns the previous setting. */
 int sgp_cg_graph_enable(int on);
 
+/* Fused blur steps (process-wide switch, default on). With a three-tap
+ * stencil (order 1), two consecutive direction steps of the blur (Section
+ * 3.2, Blur) run as one launch that forms the first step's values at the
+ * three neighbours it needs in the same order as a separate step would, so
+ * results are bitwise identical with the switch off. Returns the previous
+ * setting. */
+int sgp_blur_fuse_enable(int on);
+
 /* Kernel timing with HIP events, for benchmarks. While enabled, every
  * kernel launch of the library is bracketed by two events on its stream.
  * sgp_profile_read synchronises the recorded events and reports, for one

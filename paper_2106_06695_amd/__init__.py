@@ -25,7 +25,7 @@ from . import _lib
 __all__ = [
     "SGPError", "Lattice", "lattice_build", "lattice_mvm", "cg_solve", "lattice_mvm_grad",
     "lattice_info", "lattice_export", "lattice_free", "lattice_kernel_mvm", "profile",
-    "library_path",
+    "library_path", "cg_graph_enable", "blur_fuse_enable",
 ]
 
 SYMMETRIC, FORWARD, REVERSE = 0, 1, 2
@@ -263,6 +263,12 @@ def cg_graph_enable(on: bool) -> bool:
     """Turn graph replay of CG iterations on or off (process-wide); returns
     the previous setting. Results do not depend on it."""
     return bool(_lib.load().sgp_cg_graph_enable(1 if on else 0))
+
+
+def blur_fuse_enable(on: bool) -> bool:
+    """Turn fused two-step blur launches on or off (process-wide); returns
+    the previous setting. Results do not depend on it."""
+    return bool(_lib.load().sgp_blur_fuse_enable(1 if on else 0))
 
 
 class profile:

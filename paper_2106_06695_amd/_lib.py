@@ -28,6 +28,7 @@ SIGNATURES = {
     "lattice_free": (None, [_P]),
     "sgp_last_error": (ctypes.c_char_p, []),
     "sgp_cg_graph_enable": (ctypes.c_int, [ctypes.c_int]),
+    "sgp_blur_fuse_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_profile_reset": (ctypes.c_int, []),
     "sgp_profile_kinds": (ctypes.c_int, []),

@@ -343,12 +343,14 @@ using namespace sgp;
 namespace sgp {
 namespace {
 std::atomic<int> g_cg_graph{1};
+std::atomic<int> g_blur_fuse{1};
 }
 bool profiling() {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   return g_prof_on;
 }
 bool cg_graphs_enabled() { return g_cg_graph.load() != 0; }
+bool blur_fuse_enabled() { return g_blur_fuse.load() != 0; }
 hipStream_t capture_stream() {
   constexpr int kMaxDevices = 64;
   thread_local hipStream_t streams[kMaxDevices] = {};
@@ -458,6 +460,7 @@ void lattice_free(sgp_lattice* L) {
 
 
 int sgp_cg_graph_enable(int on) { return g_cg_graph.exchange(on != 0 ? 1 : 0); }
+int sgp_blur_fuse_enable(int on) { return g_blur_fuse.exchange(on != 0 ? 1 : 0); }
 
 int sgp_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

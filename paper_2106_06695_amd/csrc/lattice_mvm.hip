@@ -555,6 +555,126 @@ __global__ __launch_bounds__(kBlock) void k_blur(BlurArgs<TU> a) {
   }
 }
 
+// Two consecutive blur steps in one launch, for a 3-tap stencil (r = 1):
+// out(j) = sum over t2 of st[t2] * B(neighbour2(j, t2)), where B(x) = sum
+// over t1 of st[t1] * in(neighbour1(x, t1)) is the first step's value at x,
+// formed here in the same order as a launch of its own would form it (a
+// missing lattice point contributes 0). Nine rows per output row instead of
+// two launches of three; the rows mostly come from L2 and MALL.
+template <typename TU>
+struct Blur2Args {
+  const TU* in[2];
+  TU* out[2];
+  const int32_t* nbr1[2];  // first step's direction, per chain
+  const int32_t* nbr2[2];  // second step's direction
+  int64_t m;
+  int C;
+  int chains;
+  int sum_out;
+  int vec;
+  int64_t rows_per_block;
+  TU st[3];
+};
+
+template <typename TU, int VW>
+__device__ __forceinline__ void load_vw(const TU* __restrict__ in, int64_t row, int C, int c, bool vec,
+                                        TU (&v)[VW]) {
+  if (row >= 0) {
+    const TU* src = in + row * C + c;
+    if (vec) {
+      read_row<TU, VW>(src, v);
+    } else {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) v[i] = c + i < C ? src[i] : (TU)0;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < VW; ++i) v[i] = 0;
+  }
+}
+
+template <typename TU, int VW>
+__device__ __forceinline__ void blur2_rows(const TU* __restrict__ in, const int32_t* __restrict__ nb1,
+                                           const int32_t* __restrict__ nb2, int64_t m, int64_t j, int C,
+                                           int c, const TU* st, bool vec, TU (&acc)[VW]) {
+  // second-direction neighbours of j (t2 = -1, 0, +1), then their
+  // first-direction neighbours, then the nine rows
+  int64_t x[3];
+  x[0] = nb2[j];
+  x[1] = j;
+  x[2] = nb2[m + j];
+  int64_t y[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    y[a][0] = x[a] >= 0 ? (int64_t)nb1[x[a]] : -1;
+    y[a][1] = x[a];
+    y[a][2] = x[a] >= 0 ? (int64_t)nb1[m + x[a]] : -1;
+  }
+  TU v[3][3][VW];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) load_vw<TU, VW>(in, y[a][b], C, c, vec, v[a][b]);
+#pragma unroll
+  for (int i = 0; i < VW; ++i) acc[i] = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    TU bx[VW];
+#pragma unroll
+    for (int i = 0; i < VW; ++i) bx[i] = 0;
+    if (x[a] >= 0) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int i = 0; i < VW; ++i) bx[i] = fma_t(st[b], v[a][b][i], bx[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < VW; ++i) acc[i] = fma_t(st[a], bx[i], acc[i]);
+  }
+}
+
+template <typename TU, int G>
+__global__ __launch_bounds__(kBlock) void k_blur2(Blur2Args<TU> a) {
+  constexpr int VW = blur_vw<G>();
+  constexpr int LPR = G / VW;
+  constexpr int R = kBlock / LPR;
+  const int sub = threadIdx.x % LPR;
+  const int64_t j0 = xcd_block(blockIdx.x, gridDim.x) * a.rows_per_block;
+  const int64_t j1 = j0 + a.rows_per_block < a.m ? j0 + a.rows_per_block : a.m;
+  for (int64_t j = j0 + threadIdx.x / LPR; j < j1; j += R) {
+    for (int c = sub * VW; c < a.C; c += G) {
+      const bool vec = a.vec && c + VW <= a.C;
+      TU f[VW];
+      blur2_rows<TU, VW>(a.in[0], a.nbr1[0], a.nbr2[0], a.m, j, a.C, c, a.st, vec, f);
+      if (a.chains == 2) {
+        TU b[VW];
+        blur2_rows<TU, VW>(a.in[1], a.nbr1[1], a.nbr2[1], a.m, j, a.C, c, a.st, vec, b);
+        if (a.sum_out) {
+#pragma unroll
+          for (int i = 0; i < VW; ++i) f[i] = f[i] + b[i];
+        } else {
+          TU* o1 = a.out[1] + j * a.C + c;
+          if (vec) {
+            write_row<TU, VW>(o1, b);
+          } else {
+#pragma unroll
+            for (int i = 0; i < VW; ++i)
+              if (c + i < a.C) o1[i] = b[i];
+          }
+        }
+      }
+      TU* o0 = a.out[0] + j * a.C + c;
+      if (vec) {
+        write_row<TU, VW>(o0, f);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VW; ++i)
+          if (c + i < a.C) o0[i] = f[i];
+      }
+    }
+  }
+}
+
 // LDS layout of k_slice_tile: lattice rows [RC][G] (TU; also the CG
 // reduction area) | weights [P*D] (fp32) | slots [P*D] (uint16).
 struct SliceLds {
@@ -966,24 +1086,56 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   split_rows(m, kBlock / (G / blur_vw<G>()), 65536, &bblocks, &a.rows_per_block);
   a.vec = (C % Vec16<TU>::N == 0 && blur_vw<G>() % Vec16<TU>::N == 0 && aligned16(U0)) ? 1 : 0;
   const int32_t* nbr = (const int32_t*)L->nbr.ptr;
+  // Chain 0 moves between B1 and B3 and never writes U0, which chain 1 reads
+  // first; chain 1 moves between B2 and U0. Steps run in fused pairs when
+  // the stencil has three taps.
   const TU* cur[2] = {U0, U0};
-  for (int step = 0; step <= d; ++step) {
-    // chain 0: forward (or the single requested order); chain 1: reverse
-    const int k0 = (L->blur == SGP_BLUR_REVERSE) ? d - step : step;
-    const int k1 = d - step;
-    TU* dst0 = (step % 2 == 0) ? B1 : B3;
-    TU* dst1 = (step % 2 == 0) ? B2 : U0;
-    a.in[0] = cur[0];
-    a.out[0] = dst0;
-    a.nbr[0] = nbr + (int64_t)k0 * T * m;
-    a.in[1] = cur[1];
-    a.out[1] = dst1;
-    a.nbr[1] = nbr + (int64_t)k1 * T * m;
-    a.sum_out = (sym && step == d) ? 1 : 0;
-    {
-      ProfScope ps(KK_BLUR, s);
-      hipLaunchKernelGGL((k_blur<TU, G>), dim3(bblocks), dim3(kBlock), 0, s, a);
-      SGP_LAUNCH_CHECK("k_blur");
+  auto next0 = [&](const TU* c0) { return c0 == B1 ? B3 : B1; };
+  auto next1 = [&](const TU* c1) { return c1 == B2 ? U0 : B2; };
+  auto kdir = [&](int step, int chain) {
+    return chain == 0 ? ((L->blur == SGP_BLUR_REVERSE) ? d - step : step) : d - step;
+  };
+  const bool fuse = L->order == 1 && blur_fuse_enabled();
+  for (int step = 0; step <= d;) {
+    TU* dst0 = next0(cur[0]);
+    TU* dst1 = next1(cur[1]);
+    if (fuse && step + 1 <= d) {
+      Blur2Args<TU> b2;
+      b2.in[0] = cur[0];
+      b2.in[1] = cur[1];
+      b2.out[0] = dst0;
+      b2.out[1] = dst1;
+      for (int ch = 0; ch < 2; ++ch) {
+        b2.nbr1[ch] = nbr + (int64_t)kdir(step, ch) * T * m;
+        b2.nbr2[ch] = nbr + (int64_t)kdir(step + 1, ch) * T * m;
+      }
+      b2.m = m;
+      b2.C = C;
+      b2.chains = a.chains;
+      b2.sum_out = (sym && step + 1 == d) ? 1 : 0;
+      b2.vec = a.vec;
+      b2.rows_per_block = a.rows_per_block;
+      for (int t = 0; t < 3; ++t) b2.st[t] = a.st[t];
+      {
+        ProfScope ps(KK_BLUR, s);
+        hipLaunchKernelGGL((k_blur2<TU, G>), dim3(bblocks), dim3(kBlock), 0, s, b2);
+        SGP_LAUNCH_CHECK("k_blur2");
+      }
+      step += 2;
+    } else {
+      a.in[0] = cur[0];
+      a.out[0] = dst0;
+      a.nbr[0] = nbr + (int64_t)kdir(step, 0) * T * m;
+      a.in[1] = cur[1];
+      a.out[1] = dst1;
+      a.nbr[1] = nbr + (int64_t)kdir(step, 1) * T * m;
+      a.sum_out = (sym && step == d) ? 1 : 0;
+      {
+        ProfScope ps(KK_BLUR, s);
+        hipLaunchKernelGGL((k_blur<TU, G>), dim3(bblocks), dim3(kBlock), 0, s, a);
+        SGP_LAUNCH_CHECK("k_blur");
+      }
+      step += 1;
     }
     cur[0] = dst0;
     cur[1] = dst1;

@@ -71,6 +71,7 @@ enum KernelKind {
 bool profiling();
 // Process-wide switch for graph replay of CG iterations.
 bool cg_graphs_enabled();
+bool blur_fuse_enabled();
 // A per-thread, per-device stream used only to record graphs.
 hipStream_t capture_stream();
 

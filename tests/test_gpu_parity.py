@@ -332,6 +332,33 @@ def test_ws4_full_oracle(sgp, orc):
     assert _colerr(out, olat.mvm(w.values.astype(np.float64))).max() <= MVM_TOL
 
 
+@pytest.mark.parametrize("blur", ["symmetric", "forward", "reverse"])
+@pytest.mark.parametrize("seed,n,d,C", [(51, 3000, 3, 4), (52, 2500, 4, 1), (53, 20000, 11, 16),
+                                        (54, 777, 2, 3)])
+def test_blur_fused_matches_unfused(sgp, blur, seed, n, d, C):
+    """Two blur steps fused into one launch give bitwise the same MVM (fp32)
+    and CG iterates (fp64) as one launch per step; d + 1 odd leaves a single
+    last step."""
+    _note(f"blur fusion {blur} seed={seed} n={n} d={d} C={C}")
+    c = workloads.small_case(seed, n, d, channels=C, kind="mixture")
+    lat = sgp.lattice_build(_cuda(c.X), c.lengthscales, blur=blur)
+    V = _cuda(c.values)
+    prev = sgp.blur_fuse_enable(False)
+    try:
+        y0 = sgp.lattice_mvm(lat, V).cpu().numpy()
+        x0, it0, rel0 = sgp.cg_solve(lat, V, 0.1, 0.0, max_iter=6)
+        x0 = x0.cpu().numpy()
+        sgp.blur_fuse_enable(True)
+        y1 = sgp.lattice_mvm(lat, V).cpu().numpy()
+        x1, it1, rel1 = sgp.cg_solve(lat, V, 0.1, 0.0, max_iter=6)
+        np.testing.assert_array_equal(y1, y0)
+        np.testing.assert_array_equal(x1.cpu().numpy(), x0)
+        np.testing.assert_array_equal(rel1, rel0)
+    finally:
+        sgp.blur_fuse_enable(prev)
+        lat.free()
+
+
 @pytest.mark.parametrize("tol,max_iter", [(0.0, 45), (1e-6, 300)])
 def test_cg_graph_replay_matches_launches(sgp, tol, max_iter):
     """CG with iteration blocks replayed from a graph equals the launch-by-
