@@ -39,23 +39,40 @@ def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, c
         return n * D * 8 + n * C * vb + m * C * ub
     if kind == "slice":      # idx + w, U (both chains) in, out (+ p in CG)
         return n * D * 8 + chains * m * C * ub + n * C * vb + (n * C * vb if cg else 0)
-    if kind == "blur":       # per chain: U in, U out, neighbour lists
-        return chains * (2 * m * C * ub + T * m * 4)
+    if kind == "blur":       # average per launch: per chain U in, U out, neighbour lists
+        return blur_bytes_per_mvm(d, m, C, r, sym, cg) / blur_launches(d, r)
     if kind == "cg_update":  # q, r in; r out (fp64)
         return 3 * n * C * 8
-    if kind == "cg_dir":     # x, p, r in; x, p out (fp64)
-        return 5 * n * C * 8
-    if kind == "cg_init":    # b in (fp32); x, r, p out (fp64)
-        return n * C * 4 + 3 * n * C * 8
-    if kind == "cg_out":     # x in (fp64), x out (fp32)
-        return n * C * 12
+    if kind == "cg_dir":     # p, r in (fp64), x in (fp32); p out (fp64), x out (fp32)
+        return 3 * n * C * 8 + 2 * n * C * 4
+    if kind == "cg_init":    # b in (fp32); r, p out (fp64), x out (fp32)
+        return n * C * 4 + 2 * n * C * 8 + n * C * 4
+    if kind == "cg_out":     # x in, x out (fp32)
+        return n * C * 8
     if kind == "fill":
         return m * C * ub
     return 0.0
 
 
+def blur_launches(d, r):
+    """Launches per blur: with a three-tap stencil two direction steps share
+    a launch (the intermediate lattice values stay in registers)."""
+    return (d + 2) // 2 if r == 1 else d + 1
+
+
+def blur_bytes_per_mvm(d, m, C, r, sym, cg):
+    ub = 8 if cg else 4
+    T = 2 * r
+    chains = 2 if sym else 1
+    if r == 1:
+        pairs, single = (d + 1) // 2, (d + 1) % 2
+        return (pairs * chains * (2 * m * C * ub + 2 * T * m * 4)
+                + single * chains * (2 * m * C * ub + T * m * 4))
+    return (d + 1) * chains * (2 * m * C * ub + T * m * 4)
+
+
 def mvm_bytes(n, d, m, C, r, sym, cg=False):
-    return (kernel_bytes("splat", n, d, m, C, r, sym, cg) + (d + 1) * kernel_bytes("blur", n, d, m, C, r, sym, cg)
+    return (kernel_bytes("splat", n, d, m, C, r, sym, cg) + blur_bytes_per_mvm(d, m, C, r, sym, cg)
             + kernel_bytes("slice", n, d, m, C, r, sym, cg))
 
 

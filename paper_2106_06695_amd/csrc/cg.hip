@@ -7,10 +7,11 @@
 // and p. The
 // host only polls the per-column "active" flags every few iterations.
 //
-// Precision: the solver's vectors (x, r, p, q), the lattice values inside
-// its MVMs and all reductions are fp64; only the barycentric weights stay
-// fp32. In fp32 the recursive residual drifts from the true one by about
-// eps * cond(A), which at the conditioning of typical GP systems
+// Precision: the recurrence vectors (r, p, q), the lattice values inside
+// its MVMs and all reductions are fp64; the barycentric weights and x stay
+// fp32 (x is only accumulated, each update formed in fp64 and rounded once).
+// With an fp32 recurrence the recursive residual drifts from the true one by
+// about eps * cond(A), which at the conditioning of typical GP systems
 // (cond ~ 1e3..1e4) is already above a 1e-4 tolerance. The caller's rhs and
 // x are fp32. Partial sums are reduced in a fixed order, so a run is
 // reproducible given the MVM's own rounding.
@@ -85,7 +86,7 @@ __device__ inline void cg_partials(int64_t n, int C, double* __restrict__ partia
 // starting r.r.
 __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
                                                     const uint32_t* __restrict__ perm,
-                                                    double* __restrict__ x,
+                                                    float* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p,
                                                     int64_t n, int C, int64_t rows,
                                                     double* __restrict__ partials) {
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
     for (int k = 0; k < kCgRowsPerGroup; ++k) {
       if (i0 + k < n) {
         const int64_t e = (i0 + k) * C + c;
-        x[e] = 0.0;
+        x[e] = 0.0f;
         r[e] = v[k];
         p[e] = v[k];
         dot += v[k] * v[k];
@@ -155,24 +156,28 @@ __global__ __launch_bounds__(kScalarThreads) void k_cg_scalar(CgHook h, int C) {
 
 // x += alpha p with this iteration's alpha (zero for a column that was
 // already converged), then p = r + beta p for the columns still active.
-// Element-wise over the n x C arrays, two elements (one 16-byte access) per
-// step when C is even.
-__global__ __launch_bounds__(kBlock) void k_cg_dir(double* __restrict__ x, const double* __restrict__ r,
+// Element-wise over the n x C arrays, two elements (one 16-byte access of
+// r and p) per step when C is even. x is fp32: it never enters the
+// recurrence, and each update is formed in fp64 and rounded once.
+__global__ __launch_bounds__(kBlock) void k_cg_dir(float* __restrict__ x, const double* __restrict__ r,
                                                    double* __restrict__ p, int64_t nC, int C,
                                                    const CgState* __restrict__ st) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((C & 1) == 0) {
     typedef double d2 __attribute__((ext_vector_type(2)));
-    d2* x2 = (d2*)x;
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2* x2 = (f2*)x;
     d2* p2 = (d2*)p;
     const d2* r2 = (const d2*)r;
     for (int64_t h = t0; h < nC / 2; h += stride) {
       const int c = (int)((2 * h) % C);
-      const d2 pv = p2[h], xv = x2[h], rv = r2[h];
-      d2 xo, po;
-      xo[0] = __builtin_fma(st->alpha[c], pv[0], xv[0]);
-      xo[1] = __builtin_fma(st->alpha[c + 1], pv[1], xv[1]);
+      const d2 pv = p2[h], rv = r2[h];
+      const f2 xv = x2[h];
+      f2 xo;
+      d2 po;
+      xo[0] = (float)__builtin_fma(st->alpha[c], pv[0], (double)xv[0]);
+      xo[1] = (float)__builtin_fma(st->alpha[c + 1], pv[1], (double)xv[1]);
       po[0] = st->active[c] ? __builtin_fma(st->beta[c], pv[0], rv[0]) : pv[0];
       po[1] = st->active[c + 1] ? __builtin_fma(st->beta[c + 1], pv[1], rv[1]) : pv[1];
       x2[h] = xo;
@@ -182,20 +187,29 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(double* __restrict__ x, const
     for (int64_t e = t0; e < nC; e += stride) {
       const int c = (int)(e % C);
       const double pv = p[e];
-      x[e] = __builtin_fma(st->alpha[c], pv, x[e]);
+      x[e] = (float)__builtin_fma(st->alpha[c], pv, (double)x[e]);
       if (st->active[c]) p[e] = __builtin_fma(st->beta[c], pv, r[e]);
     }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_out(const double* __restrict__ x64,
+// x back to the caller's order: one thread per (row, four channels).
+__global__ __launch_bounds__(kBlock) void k_cg_out(const float* __restrict__ xs,
                                                    const uint32_t* __restrict__ perm,
-                                                   float* __restrict__ x, int64_t count, int C) {
+                                                   float* __restrict__ x, int64_t n, int C, int vec) {
+  const int ng = (C + 3) / 4;
+  const int64_t total = n * ng;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
-    const int64_t i = e / C;
-    const int c = (int)(e - i * C);
-    x[(int64_t)perm[i] * C + c] = (float)x64[e];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / ng;
+    const int c = (int)(t - i * ng) * 4;
+    const float* src = xs + i * C + c;
+    float* dst = x + (int64_t)perm[i] * C + c;
+    if (vec) {
+      *(float4*)dst = *(const float4*)src;
+    } else {
+      for (int k = 0; k < 4 && c + k < C; ++k) dst[k] = src[k];
+    }
   }
 }
 
@@ -205,7 +219,8 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   sgp_lattice* Lm = const_cast<sgp_lattice*>(L);
   const int64_t n = L->n, nC = n * C;
   int rc;
-  if ((rc = dev_reserve(L, Lm->cgvec, sizeof(double) * 4 * nC, s))) return rc;
+  // r, p, q in fp64, then x in fp32
+  if ((rc = dev_reserve(L, Lm->cgvec, (sizeof(double) * 3 + sizeof(float)) * nC, s))) return rc;
   // partial sums: one row per superchunk from the vector kernels, one row
   // per tile from the slice; then the scalar state, and the finished-block
   // counter of the slice's last-block fold
@@ -215,10 +230,10 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   const size_t st_bytes = ((sizeof(CgState) + 255) / 256) * 256;
   const size_t red_bytes = part_bytes + st_bytes + 256;
   if ((rc = dev_reserve(L, Lm->cgred, red_bytes, s))) return rc;
-  double* x64 = (double*)Lm->cgvec.ptr;
-  double* r = x64 + nC;
+  double* r = (double*)Lm->cgvec.ptr;
   double* p = r + nC;
   double* q = p + nC;
+  float* x32 = (float*)(q + nC);
   double* partials = (double*)Lm->cgred.ptr;
   CgState* st = (CgState*)((char*)Lm->cgred.ptr + part_bytes);
   unsigned* counter = (unsigned*)((char*)Lm->cgred.ptr + part_bytes + st_bytes);
@@ -240,7 +255,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   if ((rc = launch_fill_u32(counter, 1, 0u, s))) return rc;
   {
     ProfScope ps(KK_CG_INIT, s);
-    hipLaunchKernelGGL(k_cg_init, igrid, block, vlds, s, b, (const uint32_t*)L->perm.ptr, x64, r, p, n, C,
+    hipLaunchKernelGGL(k_cg_init, igrid, block, vlds, s, b, (const uint32_t*)L->perm.ptr, x32, r, p, n, C,
                        L->solve_rows, partials);
     SGP_LAUNCH_CHECK("k_cg_init");
   }
@@ -267,7 +282,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     }
     {
       ProfScope ps(KK_CG_DIR, st_);
-      hipLaunchKernelGGL(k_cg_dir, dgrid, block, 0, st_, x64, r, p, nC, C, (const CgState*)st);
+      hipLaunchKernelGGL(k_cg_dir, dgrid, block, 0, st_, x32, r, p, nC, C, (const CgState*)st);
       SGP_LAUNCH_CHECK("k_cg_dir");
     }
     return SGP_OK;
@@ -338,7 +353,10 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   }
   {
     ProfScope ps(KK_CG_OUT, s);
-    hipLaunchKernelGGL(k_cg_out, dim3(kRedBlocks), block, 0, s, x64, (const uint32_t*)L->perm.ptr, x, nC, C);
+    const int vec = (C % 4 == 0 && ((uintptr_t)x & 15u) == 0) ? 1 : 0;
+    const int64_t work = n * ((C + 3) / 4);
+    hipLaunchKernelGGL(k_cg_out, dim3((unsigned)std::min<int64_t>((work + kBlock - 1) / kBlock, 65536)), block, 0, s,
+                       (const float*)x32, (const uint32_t*)L->perm.ptr, x, n, C, vec);
     SGP_LAUNCH_CHECK("k_cg_out");
   }
   SGP_HIP(hipMemcpyAsync(host, st->iters, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
