@@ -138,7 +138,7 @@ struct TileShape {
   static constexpr bool VEC = VPT >= Vec16<TU>::N && VPT % Vec16<TU>::N == 0;
 };
 
-// LDS layout of k_splat_tile: values [P][G] (TU) | weights [P*D] (fp32) |
+// LDS layout of k_splat_tile: values [P+1][G] (TU; row P stays zero) | weights [P*D] (fp32) |
 // partial rows [maxq] (int32) | run starts [maxq+1] (uint16) | entry points
 // [P*D] (uint8) | next unclaimed run (int32).
 struct SplatLds {
@@ -148,7 +148,7 @@ template <typename TU>
 __host__ __device__ inline SplatLds splat_lds(int P, int D, int maxq, int G) {
   SplatLds o;
   const int rs = G * (int)sizeof(TU) >= 64 ? G + 16 / (int)sizeof(TU) : G;
-  size_t b = sizeof(TU) * (size_t)P * rs;
+  size_t b = sizeof(TU) * (size_t)(P + 1) * rs;
   o.w = b;
   b += sizeof(float) * (size_t)P * D;
   o.dst = b;
@@ -263,6 +263,7 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 
   int64_t item, end, step;
   xcd_items(a.items, &item, &end, &step);
+  for (int i = tid; i < S::RS; i += kSplatBlock) lv[a.P * S::RS + i] = (TU)0;  // the zero row
   if (item < end) fetch(item);
   for (; item < end; item += step) {
     const int cur_nq = nq, cur_ne = ne, cur_q0 = q0;
@@ -329,14 +330,18 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
       for (int i = 0; i < S::VW; ++i) acc[i] = 0;
       for (;;) {
         // up to four entries of the run per pass, added in entry order
+        // (a pass with fewer than four left reads the zero row with weight
+        // 0 for the rest: fma(0, 0, acc) is acc exactly, as acc is never -0)
         const int cnt = e1 - e < 4 ? e1 - e : 4;
         int lpu[4];
         TU wu[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int eu = e + (u < cnt ? u : cnt - 1);
-          lpu[u] = (int)llp[eu];
-          wu[u] = (TU)lw[eu];
+          const int lpv = (int)llp[eu];
+          const float wv = lw[eu];
+          lpu[u] = u < cnt ? lpv : a.P;
+          wu[u] = (TU)(u < cnt ? wv : 0.f);
         }
         TU x[4][S::VW];
 #pragma unroll
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int i = 0; i < S::VW; ++i) acc[i] = u < cnt ? fma_t(wu[u], x[u][i], acc[i]) : acc[i];
+          for (int i = 0; i < S::VW; ++i) acc[i] = fma_t(wu[u], x[u][i], acc[i]);
         e += cnt - 1;
         if (++e == e1) {
           TU* o = part + (int64_t)dq * a.C + cg;
