@@ -684,14 +684,18 @@ __global__ __launch_bounds__(kBlock) void k_blur2(Blur2Args<TU> a) {
 // reduction area) | weights [P*D] (fp32) | slots [P*D] (uint16).
 struct SliceLds {
   size_t w, sl, total;
+  int zrow;  // an all-zero lattice row past the staged rows and the reduction area
 };
 template <typename TU, int G>
 __host__ __device__ inline SliceLds slice_lds(int P, int D, int maxq) {
   using S = TileShape<TU, G, kSliceBlock>;
   SliceLds o;
-  size_t b = sizeof(TU) * (size_t)S::RC * S::RS;
+  const size_t row = sizeof(TU) * (size_t)S::RS;
+  size_t b = row * (size_t)S::RC;
   const size_t red = sizeof(double) * (256 * 16 + 16 * 16);  // CG tile reduction
   if (b < red) b = red;
+  o.zrow = (int)((b + row - 1) / row);
+  b = row * (size_t)(o.zrow + 1);
   o.w = b;
   b += sizeof(float) * (size_t)P * D;
   o.sl = b;
@@ -802,6 +806,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
 
   int64_t item, end, step;
   xcd_items(a.items, &item, &end, &step);
+  for (int i = tid; i < S::RS; i += kSliceBlock) lu[a.lds.zrow * S::RS + i] = (TU)0;  // the zero row
   if (item < end) {
     fetch_index(item);
     fetch(item);
@@ -875,26 +880,28 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
             const int eb = lp * a.D;
             // EB entries at a time: slots and weights, then their rows
             constexpr int EB = S::VW * sizeof(TU) >= 32 ? (CG ? 1 : 2) : 4;
+            // an entry outside this chunk (or past the point's d+1) reads
+            // the zero row with weight 0: fma(0, 0, acc) is acc exactly,
+            // as acc is never -0
             for (int j0 = 0; j0 < a.D; j0 += EB) {
               int sv[EB];
               TU wv[EB];
 #pragma unroll
               for (int u = 0; u < EB; ++u) {
                 const int j = j0 + u < a.D ? j0 + u : a.D - 1;
-                sv[u] = (int)lsl[eb + j] - r0;
-                wv[u] = (TU)lw[eb + j];
+                const int sr = (int)lsl[eb + j] - r0;
+                const float wr = lw[eb + j];
+                const bool in = (unsigned)sr < (unsigned)nr && j0 + u < a.D;
+                sv[u] = in ? sr : a.lds.zrow;
+                wv[u] = (TU)(in ? wr : 0.f);
               }
               TU x[EB][S::VW];
 #pragma unroll
-              for (int u = 0; u < EB; ++u) {
-                const bool in = (unsigned)sv[u] < (unsigned)nr;
-                read_row<TU, S::VW>(lu + (in ? sv[u] : 0) * S::RS + cl, x[u]);
-              }
+              for (int u = 0; u < EB; ++u) read_row<TU, S::VW>(lu + sv[u] * S::RS + cl, x[u]);
 #pragma unroll
-              for (int u = 0; u < EB; ++u) {
-                const bool in = (unsigned)sv[u] < (unsigned)nr && j0 + u < a.D;
+              for (int u = 0; u < EB; ++u)
 #pragma unroll
-                for (int i = 0; i < S::VW; ++i) acc[k][i] = in ? fma_t(wv[u], x[u][i], acc[k][i]) : acc[k][i];              }
+                for (int i = 0; i < S::VW; ++i) acc[k][i] = fma_t(wv[u], x[u][i], acc[k][i]);
             }
           }
         }
