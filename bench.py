@@ -176,6 +176,50 @@ def serving_bench(workers: int, count: int, rhos=(0.5, 0.9, 1.5), seed: int = 10
     return out
 
 
+def paper_sparsity_bench(sgp, X, V, w, x, args):
+    """The same step on ws3's points with lengthscales scaled to the paper's
+    lattice sparsity (ws3p, m / (n (d+1)) ~ 0.04): one warm-up step, then
+    args.paper_steps timed ones, and standalone fp32 MVMs."""
+    import torch
+    import workloads
+    scale = workloads.ws3p_scale()
+    ell = w.lengthscales * scale
+    iters = w.max_iter
+
+    def step():
+        lat = sgp.lattice_build(X, ell, blur=args.blur)
+        sgp.cg_solve(lat, V, w.noise, 0.0, max_iter=iters, x=x)
+        m = lat.m
+        lat.free()
+        return m
+
+    m = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.paper_steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.paper_steps
+    lat = sgp.lattice_build(X, ell, blur=args.blur)
+    out = torch.empty_like(V)
+    sgp.lattice_mvm(lat, V, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        sgp.lattice_mvm(lat, V, out)
+    torch.cuda.synchronize()
+    mvm_s = (time.perf_counter() - t0) / reps
+    lat.free()
+    n, d, C = w.n, w.d, w.C
+    B = mvm_bytes(n, d, m, C, 1, args.blur == "symmetric")
+    return {"workload": "ws3p: ws3 with lengthscales x %.4f (the paper's Houseelectric sparsity)" % scale,
+            "m": m, "m_over_L": m / (n * (d + 1)), "steps": args.paper_steps, "ms_per_step": ms,
+            "value": n * C * iters / (ms / 1e3), "unit": "points*ch/s",
+            "mvm_only": {"ms": mvm_s * 1e3, "points_ch_per_s": n * C / mvm_s, "algo_bytes": B,
+                         "algo_GBps": B / mvm_s / 1e9, "frac_of_hbm_peak": B / mvm_s / 1e9 / HBM_PEAK_GBS}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,11 +232,13 @@ def main(argv=None):
     ap.add_argument("--serve", type=int, default=0,
                     help="also run the serving benchmark with this many requests (0 = skip)")
     ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--paper-steps", type=int, default=3,
+                    help="timed steps of the ws3p secondary measurement (0 = skip)")
     ap.add_argument("--probe", action="store_true",
                     help="only run the short counter-collection workload")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py measures one GPU; --gpus must be 1", file=sys.stderr)
         return 2
     if args.probe:
         return probe()
@@ -279,6 +325,8 @@ def main(argv=None):
     t2 = time.perf_counter()
     lat.free()
 
+    paper = paper_sparsity_bench(sgp, X, V, w, x, args) if args.paper_steps > 0 else None
+
     line = {
         "metric": "lattice MVM points*ch/s at n=2M d=11 (build + 20 batched CG iterations per step)",
         "value": value,
@@ -310,6 +358,8 @@ def main(argv=None):
         "kernels": kernels,
         "profiled_steps": prof_steps,
     }
+    if paper is not None:
+        line["paper_sparsity"] = paper
     if args.serve > 0:
         line["serving"] = serving_bench(args.serve_workers, args.serve)
     if args.cpu_sample > 0:

@@ -14,6 +14,10 @@ which are not available here; every array is synthetic:
   ws3  n=2,000,000 d=11  mixture of 50 Gaussians, l ~ logU[0.5, 2],
                          C = 16 (1 target ~ N(0,1) + 15 Rademacher probes),
                          noise 0.05, 20 fixed CG iterations
+  ws3p ws3 with every lengthscale scaled by the factor in ws3p_scale.json,
+                         which gives the lattice the paper's sparsity for
+                         Houseelectric (m / (n (d+1)) ~ 0.041; written by
+                         paper_sparsity.py from the oracle's lattice)
   ws4  n=1,000,000 d=16  X ~ U[-1, 1]^16, l ~ logU[0.3, 3], C = 8 ~ N(0,1)
   ws5  serving stream: 256 requests, n ~ logU[1e3, 3e5], d ~ U{3..20},
                          mixture of 20, l ~ logU[0.5, 2], C = 8, noise 0.05,
@@ -25,10 +29,13 @@ X is fp32 (row-major n x d), lengthscales fp64 (host constants), values fp32.
 from __future__ import annotations
 
 import dataclasses
+import json
+import os
+
 import numpy as np
 
 __all__ = [
-    "mixture", "Workload", "ws1", "ws2", "ws3", "ws4", "ws5_requests",
+    "mixture", "Workload", "ws1", "ws2", "ws3", "ws3p", "ws3p_scale", "ws4", "ws5_requests",
     "small_case", "by_name",
 ]
 
@@ -108,6 +115,17 @@ def ws3(seed: int = 1003, n: int = 2_000_000, channels: int = 16) -> Workload:
     return Workload("ws3", X, ell, V, noise=0.05, tol=0.0, max_iter=20)
 
 
+def ws3p_scale() -> float:
+    """The lengthscale factor stored by paper_sparsity.py."""
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "ws3p_scale.json")) as f:
+        return float(json.load(f)["scale"])
+
+
+def ws3p(seed: int = 1003, n: int = 2_000_000, channels: int = 16) -> Workload:
+    w = ws3(seed, n, channels)
+    return dataclasses.replace(w, name="ws3p", lengthscales=w.lengthscales * ws3p_scale())
+
+
 def ws4(seed: int = 1004, n: int = 1_000_000) -> Workload:
     rng = np.random.default_rng(seed)
     X = rng.uniform(-1.0, 1.0, size=(n, 16)).astype(np.float32)
@@ -171,4 +189,4 @@ def ws5_requests(seed: int = 1005, count: int = 256, mean_gap_s: float = 0.01,
 
 
 def by_name(name: str, **kw) -> Workload:
-    return {"ws1": ws1, "ws2": ws2, "ws3": ws3, "ws4": ws4}[name](**kw)
+    return {"ws1": ws1, "ws2": ws2, "ws3": ws3, "ws3p": ws3p, "ws4": ws4}[name](**kw)
