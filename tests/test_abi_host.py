@@ -114,3 +114,18 @@ def test_python_binding_rejects_cpu_tensors():
     import paper_2106_06695_amd as sgp
     with pytest.raises(TypeError):
         sgp.lattice_build(torch.zeros(4, 2), [1.0, 1.0])
+
+
+def test_ws3p_scale_matches_paper_sparsity():
+    """The stored lengthscale factor of ws3p (written from the oracle's lattice
+    by workloads/paper_sparsity.py) gives the paper's Houseelectric ratio
+    m / (n (d+1)) = 1,000,190 / (2,049,280 * 12) to within 0.5%."""
+    import json
+    import os
+    import workloads
+    path = os.path.join(os.path.dirname(workloads.__file__), "ws3p_scale.json")
+    rec = json.load(open(path))
+    target = 1_000_190 / (2_049_280 * 12)
+    assert abs(rec["target"] - target) < 1e-12
+    assert abs(rec["m_over_L"] - target) <= 0.005 * target
+    assert 0.5 < rec["scale"] < 1.0 and workloads.ws3p_scale() == rec["scale"]

@@ -332,6 +332,22 @@ def test_ws4_full_oracle(sgp, orc):
     assert _colerr(out, olat.mvm(w.values.astype(np.float64))).max() <= MVM_TOL
 
 
+def test_ws3p_lattice_size_matches_oracle(sgp):
+    """At full size (n = 2M, d = 11) the lattice of ws3p has exactly the
+    number of lattice points the oracle found when the factor was chosen."""
+    import json
+    import os
+    _note("ws3p lattice size")
+    w = workloads.ws3p()
+    rec = json.load(open(os.path.join(os.path.dirname(workloads.__file__), "ws3p_scale.json")))
+    m_oracle = round(rec["m_over_L"] * w.n * (w.d + 1))
+    lat = sgp.lattice_build(_cuda(w.X), w.lengthscales)
+    try:
+        assert lat.m == m_oracle
+    finally:
+        lat.free()
+
+
 @pytest.mark.parametrize("blur", ["symmetric", "forward", "reverse"])
 @pytest.mark.parametrize("seed,n,d,C", [(51, 3000, 3, 4), (52, 2500, 4, 1), (53, 20000, 11, 16),
                                         (54, 777, 2, 3)])
