@@ -80,7 +80,7 @@ def mvm_bytes(n, d, m, C, r, sym, cg=False):
 # traffic is reported only while they are unchanged.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ws3_traffic.json")
 TRAFFIC_SOURCES = ["paper_2106_06695_amd/csrc/lattice_mvm.hip", "paper_2106_06695_amd/csrc/sgp_internal.h",
-                   "paper_2106_06695_amd/csrc/cg.hip"]
+                   "paper_2106_06695_amd/csrc/cg.hip", "paper_2106_06695_amd/csrc/cg_step.h"]
 
 
 def sources_digest() -> dict:
