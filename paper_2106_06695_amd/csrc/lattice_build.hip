@@ -738,7 +738,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_fill(const sgp_entry* __r
 // entry (canonical numbering) and the smallest sorted-order entry (first
 // touch) are kept with one atomic each per (tile, slot). Every entry's key
 // must equal its representative's; one that differs is a hash collision.
-constexpr int kInsThreads = 256;
+constexpr int kInsThreads = 512;
 constexpr int kInsSpan = 4;                          // consecutive entries per thread
 constexpr int kInsEntries = kInsThreads * kInsSpan;  // entries per block, at most
 constexpr int kInsTable = 2 * kInsEntries;           // LDS table slots (load factor <= 1/2)
@@ -837,11 +837,18 @@ __global__ __launch_bounds__(kInsThreads) void k_tile_insert(
   for (int u = 0; u < kInsSpan; ++u) rep[u] = ts[u] >= 0 ? (int)S.table[ts[u]] : -1;
   __syncthreads();  // the hashes are no longer read: representatives take (slot, min caller entry)
   uint32_t* g32 = reinterpret_cast<uint32_t*>(S.h);
+  // the representatives' first probes go out together; a slot taken by
+  // another hash (rare) continues probing on its own
+  unsigned long long prev[kInsSpan];
+#pragma unroll
+  for (int u = 0; u < kInsSpan; ++u)
+    prev[u] = rep[u] == e0 + u ? atomicCAS(&tab[hv[u] & mask], kEmpty, hv[u]) : kEmpty;
 #pragma unroll
   for (int u = 0; u < kInsSpan; ++u) {
     const int e = e0 + u;
     if (rep[u] != e) continue;
-    const int64_t sl = table_claim(tab, mask, hv[u]);
+    int64_t sl = (int64_t)(hv[u] & mask);
+    if (prev[u] != kEmpty && prev[u] != hv[u]) sl = table_claim(tab, mask, hv[u]);
     if (sl < 0) atomicOr(flags, BF_TABLE_FULL);
     g32[2 * e] = (uint32_t)sl;
     g32[2 * e + 1] = 0xffffffffu;
