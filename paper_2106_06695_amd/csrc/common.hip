@@ -447,7 +447,9 @@ int lattice_export(const sgp_lattice* L, int32_t* keys, int32_t* idx, float* w, 
 void lattice_free(sgp_lattice* L) {
   if (!L) return;
   (void)hipSetDevice(L->device);
-  (void)wait_last_use(L);
+  // wait for the last use without replacing the thread's error message: a
+  // failed build frees its lattice on the way out and reports its own error
+  if (L->last_use) (void)hipEventSynchronize(L->last_use);
   for (DevBuf* b : {&L->perm, &L->loc, &L->ws, &L->tile_off, &L->stile_off, &L->tile_verts, &L->run_rel,
                    &L->ent_lp, &L->ent_w, &L->occ_ptr, &L->run_dst, &L->row_vert, &L->nbr, &L->int2can, &L->keys})
     dev_free(*b);

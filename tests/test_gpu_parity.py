@@ -136,6 +136,16 @@ def test_mvm_parity_dims(sgp, orc, d, order, kernel):
     assert _colerr(out, ref).max() <= MVM_TOL
 
 
+def test_mvm_parity_many_lattice_points(sgp, orc):
+    """More than 2^20 lattice points: the tile sort then keys on 64 bits."""
+    _note("mvm with m > 2^20")
+    w = workloads.small_case(61, 55_000, 20, channels=2, kind="uniform", ell_range=(0.05, 0.1))
+    lat, olat = _build_both(sgp, orc, w.X, w.lengthscales)
+    assert lat.m == olat.m > (1 << 20)
+    out = sgp.lattice_mvm(lat, _cuda(w.values)).cpu().numpy()
+    assert _colerr(out, olat.mvm(w.values.astype(np.float64))).max() <= MVM_TOL
+
+
 def test_mvm_reuse_and_many_handles(sgp, orc):
     _note("mvm reuse")
     w = workloads.small_case(60, 1000, 4, channels=5, kind="normal")
