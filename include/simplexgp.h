@@ -178,6 +178,27 @@ int sgp_cg_graph_enable(int on);
  * setting. */
 int sgp_blur_fuse_enable(int on);
 
+/* Autotuning of the MVM's launch shape (the multi-column lattice filter of
+ * Section 3.2, batched as in the mBCG solver of Section 2). Times every
+ * candidate on lattice L for C columns, fp64 (the CG path, C <= 64) or
+ * fp32 (lattice_mvm), with reps timed MVMs each after one warm-up: the
+ * channel chunk width (the widest that fits the LDS budget, half, quarter)
+ * times the resident blocks per CU of the persistent splat and slice (as
+ * many as fit, or one). The fastest is kept process-wide for lattices of
+ * the same d, column width class (C rounded up to a power of two), element
+ * size and size class (m rounded up to a power of two) and is used by later
+ * lattice_mvm and cg_solve calls; no choice changes any result bit.
+ * Allocates two n x C work arrays for the duration of the call and
+ * synchronises the stream. choice (may be NULL) receives {chunk width,
+ * splat blocks per CU, slice blocks per CU} (0: as many as fit);
+ * ms_per_mvm (may be NULL) the fastest time. Returns SGP_EINVAL for a NULL
+ * lattice, C < 1, C > 64 in fp64 or reps < 1. */
+int sgp_autotune(const sgp_lattice* L, int32_t C, int32_t fp64, int32_t reps, void* stream,
+                 int32_t* choice, float* ms_per_mvm);
+
+/* Forget every autotuned choice (later calls use the default shapes). */
+int sgp_autotune_reset(void);
+
 /* Kernel timing with HIP events, for benchmarks. While enabled, every
  * kernel launch of the library is bracketed by two events on its stream.
  * sgp_profile_read synchronises the recorded events and reports, for one

@@ -25,7 +25,7 @@ from . import _lib
 __all__ = [
     "SGPError", "Lattice", "lattice_build", "lattice_mvm", "cg_solve", "lattice_mvm_grad",
     "lattice_info", "lattice_export", "lattice_free", "lattice_kernel_mvm", "profile",
-    "library_path", "cg_graph_enable", "blur_fuse_enable",
+    "library_path", "cg_graph_enable", "blur_fuse_enable", "autotune", "autotune_reset",
 ]
 
 SYMMETRIC, FORWARD, REVERSE = 0, 1, 2
@@ -269,6 +269,24 @@ def blur_fuse_enable(on: bool) -> bool:
     """Turn fused two-step blur launches on or off (process-wide); returns
     the previous setting. Results do not depend on it."""
     return bool(_lib.load().sgp_blur_fuse_enable(1 if on else 0))
+
+
+def autotune(lat: Lattice, C: int, fp64: bool = True, reps: int = 3) -> dict:
+    """Time the MVM's launch-shape candidates on this lattice for C columns
+    and keep the fastest for lattices of the same shape class; see
+    sgp_autotune in include/simplexgp.h. Results do not depend on it."""
+    lib = _lib.load()
+    choice = (ctypes.c_int32 * 3)()
+    ms = ctypes.c_float()
+    _check(lib.sgp_autotune(lat.handle, int(C), 1 if fp64 else 0, int(reps), _stream(),
+                            ctypes.cast(choice, ctypes.c_void_p), ctypes.cast(ctypes.pointer(ms), ctypes.c_void_p)))
+    return {"chunk": choice[0], "splat_blocks_per_cu": choice[1], "slice_blocks_per_cu": choice[2],
+            "ms_per_mvm": ms.value}
+
+
+def autotune_reset() -> None:
+    """Forget every autotuned launch choice."""
+    _check(_lib.load().sgp_autotune_reset())
 
 
 class profile:

@@ -29,6 +29,9 @@ SIGNATURES = {
     "sgp_last_error": (ctypes.c_char_p, []),
     "sgp_cg_graph_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_blur_fuse_enable": (ctypes.c_int, [ctypes.c_int]),
+    "sgp_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sgp_autotune_reset": (ctypes.c_int, []),
     "sgp_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_profile_reset": (ctypes.c_int, []),
     "sgp_profile_kinds": (ctypes.c_int, []),

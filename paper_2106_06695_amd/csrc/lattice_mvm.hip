@@ -29,6 +29,9 @@
 // Row ranges of consecutive blocks go to the same XCD (blocks are dealt
 // round-robin over the 8 XCDs), so tiles that share lattice points share
 // an L2.
+#include <mutex>
+#include <vector>
+
 #include "cg_step.h"
 #include "sgp_internal.h"
 
@@ -1004,10 +1007,45 @@ int cu_count() {
 // Blocks of a persistent tile kernel: as many as can be resident, at most
 // one per work item. A kernel staging more than 64 KiB of LDS is first
 // allowed to.
-unsigned persistent_grid(const void* kernel, int threads, size_t lds, int64_t items) {
+// Launch choices an autotuning run can set: the channel chunk width and the
+// resident blocks per CU of the persistent splat and slice (0: as many as
+// the occupancy allows). None of them changes a result: every sum is formed
+// in an order that depends on neither the chunk width nor the grid.
+struct LaunchChoice {
+  int g;
+  int splat_bpc;
+  int slice_bpc;
+};
+struct TuneEntry {
+  int d, elem, g0, mlog;
+  LaunchChoice c;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;                  // process-wide, keyed by lattice shape
+thread_local const LaunchChoice* g_force = nullptr;  // set while candidates are timed
+
+int mlog_of(int64_t m) {
+  int b = 0;
+  while (((int64_t)1 << b) < m) ++b;
+  return b;
+}
+
+bool tune_find(const sgp_lattice* L, int C, int elem, LaunchChoice* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const TuneEntry& e : g_tune)
+    if (e.d == L->d && e.elem == elem && e.g0 == lanes_for(C) && e.mlog == mlog_of(L->m)) {
+      *out = e.c;
+      return true;
+    }
+  return false;
+}
+
+unsigned persistent_grid(const void* kernel, int threads, size_t lds, int64_t items, int chosen_bpc) {
   if (lds > 65536) (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
   int bpc = tuning().blocks_per_cu;
+  if (bpc <= 0) bpc = chosen_bpc;
   if (bpc <= 0) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb < 1) {
@@ -1043,7 +1081,7 @@ void split_rows(int64_t rows, int R, int64_t cap, unsigned* blocks, int64_t* row
 
 template <typename TU, int G>
 int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out, hipStream_t s,
-          TU noise, const TU* p, const CgHook* hook) {
+          TU noise, const TU* p, const CgHook* hook, const LaunchChoice& lc) {
   const int d = L->d, D = d + 1, T = 2 * L->order;
   const int64_t m = L->m, mC = m * C;
   TU* U0 = (TU*)L->ubuf.ptr;
@@ -1068,7 +1106,8 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
     sa.vec_v = (TileShape<TU, G, kSplatBlock>::VEC && !perm && C == G && aligned16(V)) ? 1 : 0;
     sa.cvec = (C % Vec16<TU>::N == 0 && aligned16(part)) ? 1 : 0;
     sa.lds = splat_lds<TU>(P, D, L->max_tile_pieces, G);
-    const unsigned grid = persistent_grid((const void*)&k_splat_tile<TU, G>, kSplatBlock, sa.lds.total, sa.items);
+    const unsigned grid =
+        persistent_grid((const void*)&k_splat_tile<TU, G>, kSplatBlock, sa.lds.total, sa.items, lc.splat_bpc);
     hipLaunchKernelGGL((k_splat_tile<TU, G>), dim3(grid), dim3(kSplatBlock), sa.lds.total, s,
                        (const int32_t*)L->stile_off.ptr, (const uint16_t*)L->run_rel.ptr,
                        (const int32_t*)L->run_dst.ptr, (const uint8_t*)L->ent_lp.ptr,
@@ -1172,11 +1211,13 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   const float* ws = (const float*)L->ws.ptr;
   const uint32_t* mperm = (const uint32_t*)L->perm.ptr;
   if (hook) {
-    const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, true>, kSliceBlock, la.lds.total, la.items);
+    const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, true>, kSliceBlock, la.lds.total,
+                                          la.items, lc.slice_bpc);
     hipLaunchKernelGGL((k_slice_tile<TU, G, true>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
                        tverts, loc, ws, (const TU*)cur[0], out, perm, p, *hook, mperm, la);
   } else {
-    const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, false>, kSliceBlock, la.lds.total, la.items);
+    const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, false>, kSliceBlock, la.lds.total,
+                                          la.items, lc.slice_bpc);
     hipLaunchKernelGGL((k_slice_tile<TU, G, false>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
                        tverts, loc, ws, (const TU*)cur[0], out, perm, (const TU*)nullptr, CgHook{},
                        mperm, la);
@@ -1207,14 +1248,21 @@ int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C,
   int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf,
                        sizeof(TU) * (4 * L->m + L->npiece + 2 * gather_ranges(L)) * (size_t)C, s);
   if (rc) return rc;
-  switch (chunk_lanes(L, C, sizeof(TU))) {
-    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, hook);
-    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, p, hook);
-    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, p, hook);
-    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, p, hook);
-    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, p, hook);
-    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, p, hook);
-    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, p, hook);
+  const int gmax = chunk_lanes(L, C, sizeof(TU));
+  LaunchChoice lc{gmax, 0, 0};
+  if (g_force)
+    lc = *g_force;
+  else
+    (void)tune_find(L, C, (int)sizeof(TU), &lc);
+  if (lc.g < 1 || lc.g > gmax || (lc.g & (lc.g - 1))) lc.g = gmax;  // never wider than the LDS allows
+  switch (lc.g) {
+    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, hook, lc);
+    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, p, hook, lc);
+    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, p, hook, lc);
+    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, p, hook, lc);
+    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, p, hook, lc);
+    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, p, hook, lc);
+    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, p, hook, lc);
   }
 }
 
@@ -1232,6 +1280,88 @@ int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t 
 
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s) {
   return mvm_dispatch<double>(L, V, nullptr, C, out, s, 0.0, nullptr, nullptr);
+}
+
+// Times every candidate launch choice on this lattice and keeps the fastest
+// for lattices of the same shape.
+int autotune(const sgp_lattice* L, int C, bool fp64, int reps, hipStream_t s, int32_t* choice,
+             float* best_ms) {
+  const int elem = fp64 ? 8 : 4;
+  const int gmax = chunk_lanes(L, C, elem);
+  DevBuf buf;
+  const size_t bytes = (size_t)elem * (size_t)L->n * (size_t)C;
+  int rc = dev_alloc(buf, 2 * bytes, s);
+  if (rc) return rc;
+  struct Cleanup {
+    DevBuf* b;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Cleanup() {
+      g_force = nullptr;
+      (void)hipStreamSynchronize(s);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      dev_free(*b);
+    }
+  } cleanup{&buf, s};
+  // values near 1 (every 32-bit word 0x3F800000 for fp32, 0x3FF00000 for fp64)
+  if ((rc = launch_fill_u32((uint32_t*)buf.ptr, bytes / 4, fp64 ? 0x3FF00000u : 0x3F800000u, s))) return rc;
+  SGP_HIP(hipEventCreate(&cleanup.e0));
+  SGP_HIP(hipEventCreate(&cleanup.e1));
+  void* V = buf.ptr;
+  void* out = (char*)buf.ptr + bytes;
+  auto run = [&]() {
+    return fp64 ? mvm_f64(L, (const double*)V, C, (double*)out, s)
+                : mvm_into(L, (const float*)V, C, (float*)out, s);
+  };
+  LaunchChoice best{gmax, 0, 0};
+  float best_t = -1.f;
+  for (int g = gmax; g >= 1 && g >= gmax / 4; g >>= 1) {
+    for (int sb = 0; sb <= 1; ++sb) {
+      for (int lb = 0; lb <= 1; ++lb) {
+        const LaunchChoice cand{g, sb, lb};
+        g_force = &cand;
+        if ((rc = run())) return rc;  // warm-up (sizes buffers, sets LDS limits)
+        SGP_HIP(hipEventRecord(cleanup.e0, s));
+        for (int r = 0; r < reps; ++r)
+          if ((rc = run())) return rc;
+        SGP_HIP(hipEventRecord(cleanup.e1, s));
+        SGP_HIP(hipEventSynchronize(cleanup.e1));
+        float ms = 0.f;
+        SGP_HIP(hipEventElapsedTime(&ms, cleanup.e0, cleanup.e1));
+        ms /= (float)reps;
+        if (best_t < 0.f || ms < best_t) {
+          best_t = ms;
+          best = cand;
+        }
+        g_force = nullptr;
+      }
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneEntry e{L->d, elem, lanes_for(C), mlog_of(L->m), best, best_t};
+    bool found = false;
+    for (TuneEntry& x : g_tune)
+      if (x.d == e.d && x.elem == e.elem && x.g0 == e.g0 && x.mlog == e.mlog) {
+        x = e;
+        found = true;
+      }
+    if (!found) g_tune.push_back(e);
+  }
+  if (choice) {
+    choice[0] = best.g;
+    choice[1] = best.splat_bpc;
+    choice[2] = best.slice_bpc;
+  }
+  if (best_ms) *best_ms = best_t;
+  mark_use(L, s);
+  return SGP_OK;
+}
+
+void autotune_reset() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
 }
 
 }  // namespace sgp
@@ -1258,4 +1388,22 @@ extern "C" int lattice_mvm(const sgp_lattice* L, const float* values, int32_t C,
   const int rc = mvm_into(L, values, C, out, (hipStream_t)stream);
   if (rc == SGP_OK) mark_use(L, (hipStream_t)stream);
   return rc;
+}
+
+extern "C" int sgp_autotune(const sgp_lattice* L, int32_t C, int32_t fp64, int32_t reps, void* stream,
+                            int32_t* choice, float* ms_per_mvm) {
+  if (!L) {
+    set_error("sgp_autotune: NULL lattice");
+    return SGP_EINVAL;
+  }
+  if (C < 1 || (fp64 && C > kMaxCgCols) || reps < 1) {
+    set_error("sgp_autotune: need C >= 1 (at most %d in fp64) and reps >= 1", kMaxCgCols);
+    return SGP_EINVAL;
+  }
+  return autotune(L, C, fp64 != 0, reps, (hipStream_t)stream, choice, ms_per_mvm);
+}
+
+extern "C" int sgp_autotune_reset(void) {
+  autotune_reset();
+  return SGP_OK;
 }

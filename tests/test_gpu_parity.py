@@ -385,6 +385,32 @@ def test_blur_fused_matches_unfused(sgp, blur, seed, n, d, C):
         lat.free()
 
 
+@pytest.mark.parametrize("C,fp64", [(5, True), (16, True), (3, False)])
+def test_autotune_keeps_results(sgp, C, fp64):
+    """Autotuned launch shapes give bitwise the same MVM and CG results, and
+    the choice is one of the candidates."""
+    _note(f"autotune C={C} fp64={fp64}")
+    c = workloads.small_case(71 + C, 20000, 6, channels=C, kind="mixture")
+    lat = sgp.lattice_build(_cuda(c.X), c.lengthscales)
+    V = _cuda(c.values)
+    sgp.autotune_reset()
+    try:
+        y0 = sgp.lattice_mvm(lat, V).cpu().numpy()
+        x0, _, rel0 = sgp.cg_solve(lat, V, 0.1, 0.0, max_iter=6)
+        x0 = x0.cpu().numpy()
+        ch = sgp.autotune(lat, C, fp64=fp64, reps=2)
+        assert ch["chunk"] in (1, 2, 4, 8, 16, 32, 64) and ch["ms_per_mvm"] > 0
+        assert ch["splat_blocks_per_cu"] in (0, 1) and ch["slice_blocks_per_cu"] in (0, 1)
+        y1 = sgp.lattice_mvm(lat, V).cpu().numpy()
+        x1, _, rel1 = sgp.cg_solve(lat, V, 0.1, 0.0, max_iter=6)
+        np.testing.assert_array_equal(y1, y0)
+        np.testing.assert_array_equal(x1.cpu().numpy(), x0)
+        np.testing.assert_array_equal(rel1, rel0)
+    finally:
+        sgp.autotune_reset()
+        lat.free()
+
+
 @pytest.mark.parametrize("tol,max_iter", [(0.0, 45), (1e-6, 300)])
 def test_cg_graph_replay_matches_launches(sgp, tol, max_iter):
     """CG with iteration blocks replayed from a graph equals the launch-by-
