@@ -134,7 +134,7 @@ __device__ int64_t table_find(const unsigned long long* tab, unsigned long long 
 // remainder-0 points is gathered in LDS and merged into the global words
 // once per block (one block per group would put millions of atomics on the
 // same few words).
-constexpr int kElevateBlocks = 1024;
+constexpr int kElevateBlocks = 4096;
 __global__ __launch_bounds__(kBlock) void k_elevate(SimplexArgs a) {
   __shared__ double sh_a[kBlock];    // scaled inputs c_j, then residuals
   __shared__ double sh_q[kBlock];    // residuals / (d+1) in rank order
