@@ -97,27 +97,19 @@ struct SimplexArgs {
   int32_t* rmax;
 };
 
-// Returns the slot of hash h, claiming an empty one if needed; -1 if full.
-__device__ int64_t table_insert(unsigned long long* tab, unsigned long long mask,
-                                unsigned long long h) {
-  unsigned long long s = h & mask;
-  for (unsigned long long probe = 0; probe <= mask; ++probe) {
-    unsigned long long cur = __hip_atomic_load(&tab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (cur == h) return (int64_t)s;
-    if (cur == kEmpty) {
-      unsigned long long prev = atomicCAS(&tab[s], kEmpty, h);
-      if (prev == kEmpty || prev == h) return (int64_t)s;
-    }
-    s = (s + 1) & mask;
-  }
-  return -1;
-}
+// Linear probing stops after maxp slots (kMaxProbe with the full table,
+// kMaxProbeReduced with a reduced one): a longer sequence counts as a full
+// table, and a build that started with a reduced table then retries with
+// the full one. Lookups use the same bound, so they find every key that
+// was inserted.
+constexpr unsigned long long kMaxProbe = 4096;
+constexpr unsigned long long kMaxProbeReduced = 32;
 
 // Read-only lookup; -1 if h is not in the table.
 __device__ int64_t table_find(const unsigned long long* tab, unsigned long long mask,
-                              unsigned long long h) {
+                              unsigned long long h, unsigned long long maxp) {
   unsigned long long s = h & mask;
-  for (unsigned long long probe = 0; probe <= mask; ++probe) {
+  for (unsigned long long probe = 0; probe <= mask && probe < maxp; ++probe) {
     const unsigned long long cur = tab[s];
     if (cur == h) return (int64_t)s;
     if (cur == kEmpty) return -1;
@@ -342,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict_
                                                       const unsigned long long* __restrict__ tab,
                                                       const uint32_t* __restrict__ tab_first,
                                                       unsigned long long mask,
-                                                      HashCoef hc,
+                                                      HashCoef hc, unsigned long long maxp,
                                                       int32_t* __restrict__ nbr) {
   const int D = d + 1, T = 2 * r;
   const int64_t total = m * D;
@@ -358,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict_
       for (int l = 0; l < d; ++l) h = hash_acc(h, hc.a[l], kj[l] + (l == k ? -t * d : t));
       h = hash_final(h);
       int32_t found = -1;
-      const int64_t s = table_find(tab, mask, h);
+      const int64_t s = table_find(tab, mask, h, maxp);
       if (s >= 0) {
         const uint32_t v = tab_first[s];
         const int64_t cand = (int64_t)(v & ~kCanonBit);
@@ -756,9 +748,10 @@ __device__ __forceinline__ int32_t staged_coord(const TileInsertLds& S, int lp, 
 }
 
 // Global slot of hash h: claimed by compare-and-swap if empty; -1 if full.
-__device__ int64_t table_claim(unsigned long long* tab, unsigned long long mask, unsigned long long h) {
+__device__ int64_t table_claim(unsigned long long* tab, unsigned long long mask, unsigned long long h,
+                               unsigned long long maxp) {
   unsigned long long s = h & mask;
-  for (unsigned long long probe = 0; probe <= mask; ++probe) {
+  for (unsigned long long probe = 0; probe <= mask && probe < maxp; ++probe) {
     const unsigned long long prev = atomicCAS(&tab[s], kEmpty, h);
     if (prev == kEmpty || prev == h) return (int64_t)s;
     s = (s + 1) & mask;
@@ -770,7 +763,7 @@ __global__ __launch_bounds__(kInsThreads) void k_tile_insert(
     const uint32_t* __restrict__ perm, const int32_t* __restrict__ pt_r0,
     const uint8_t* __restrict__ pt_rank, int64_t n, int d, int P, unsigned long long* __restrict__ tab,
     uint32_t* __restrict__ tab_first, uint32_t* __restrict__ first2, unsigned long long mask,
-    HashCoef hc, int32_t* __restrict__ slot, int32_t* __restrict__ slot_s,
+    HashCoef hc, unsigned long long maxp, int32_t* __restrict__ slot, int32_t* __restrict__ slot_s,
     uint32_t* __restrict__ flags) {
   __shared__ TileInsertLds S;
   const int D = d + 1;
@@ -848,7 +841,7 @@ __global__ __launch_bounds__(kInsThreads) void k_tile_insert(
     const int e = e0 + u;
     if (rep[u] != e) continue;
     int64_t sl = (int64_t)(hv[u] & mask);
-    if (prev[u] != kEmpty && prev[u] != hv[u]) sl = table_claim(tab, mask, hv[u]);
+    if (prev[u] != kEmpty && prev[u] != hv[u]) sl = table_claim(tab, mask, hv[u], maxp);
     if (sl < 0) atomicOr(flags, BF_TABLE_FULL);
     g32[2 * e] = (uint32_t)sl;
     g32[2 * e + 1] = 0xffffffffu;
@@ -955,9 +948,15 @@ int bits_for(uint64_t range) {  // bits to hold values 0..range
   return b;
 }
 
+// shrink > 0 starts from a table 2^shrink times smaller than the bound
+// L / load_factor (most lattices have far fewer distinct points than
+// simplex vertices); *grow reports that it filled up, and the caller then
+// repeats the attempt with the full table.
 int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_factor,
-                  unsigned long long seed, hipStream_t st, uint32_t* host_word, bool* retry) {
+                  unsigned long long seed, int shrink, hipStream_t st, uint32_t* host_word, bool* retry,
+                  bool* grow) {
   *retry = false;
+  *grow = false;
   const int d = L->d, D = d + 1, T = 2 * L->order;
   const int64_t n = L->n;
   const int64_t Lel = n * D;
@@ -968,6 +967,9 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
               (long long)cap);
     return SGP_EINVAL;
   }
+  if (shrink > 0 && (cap >> shrink) >= 1024) cap >>= shrink;
+  else shrink = 0;
+  const unsigned long long maxp = shrink > 0 ? kMaxProbeReduced : kMaxProbe;
   const int64_t nb = (Lel + kChunk - 1) / kChunk;
   const HashCoef hc = hash_coef(seed);
 
@@ -1109,7 +1111,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     const int Pi = kInsEntries / D;
     hipLaunchKernelGGL(k_tile_insert, dim3((unsigned)((n + Pi - 1) / Pi)), dim3(kInsThreads), 0, st,
                        (const uint32_t*)perm, (const int32_t*)pt_r0, (const uint8_t*)pt_rank, n, d, Pi, tab,
-                       tab_first, first2, (unsigned long long)(cap - 1), hc, slot, slot_s, words);
+                       tab_first, first2, (unsigned long long)(cap - 1), hc, maxp, slot, slot_s, words);
     SGP_LAUNCH_CHECK("k_tile_insert");
   }
   {
@@ -1128,6 +1130,11 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   const uint32_t flags = host_word[0];
   const int64_t m = host_word[1];
   if (flags & BF_TABLE_FULL) {
+    if (shrink > 0) {  // the reduced table was too small: repeat with the full one
+      tr.idle = true;
+      *grow = true;
+      return SGP_OK;
+    }
     set_error("lattice_build: hash table full");
     return SGP_EHASH;
   }
@@ -1159,7 +1166,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     ProfScope ps(KK_NEIGHBORS, st);
     hipLaunchKernelGGL(k_neighbors, dim3(grid_for(m * D, kBlock, 16384)), dim3(kBlock), 0, st,
                        (const int32_t*)L->keys.ptr, m, d, L->order, tab, tab_first,
-                       (unsigned long long)(cap - 1), hc, nbr_can);
+                       (unsigned long long)(cap - 1), hc, maxp, nbr_can);
     SGP_LAUNCH_CHECK("k_neighbors");
   }
   // ---- internal numbering: lattice points by first touch in sorted order
@@ -1372,9 +1379,17 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
     }
   }
   bool retry = true;
-  for (int attempt = 0; rc == SGP_OK && retry && attempt < 4; ++attempt) {
+  int shrink = 3;  // first try a table 8x smaller than the bound
+  for (int attempt = 0; rc == SGP_OK && retry && attempt < 4;) {
     const unsigned long long seed = 0x5157a11ce5eedull + 0x9e3779b97f4a7c15ull * (unsigned long long)attempt;
-    rc = build_attempt(L, X, f, (double)o.load_factor, seed, st, host_word, &retry);
+    bool grow = false;
+    rc = build_attempt(L, X, f, (double)o.load_factor, seed, shrink, st, host_word, &retry, &grow);
+    if (rc == SGP_OK && grow) {
+      shrink = 0;
+      retry = true;
+      continue;
+    }
+    ++attempt;
   }
   if (rc == SGP_OK && retry) {
     set_error("lattice_build: hash verification failed after 4 seeds");
