@@ -243,20 +243,27 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
   return incl - v;
 }
 
-__device__ __forceinline__ bool is_first(const int32_t* slot, const uint32_t* tab_first, int64_t e) {
-  const int32_t s = slot[e];
-  return s >= 0 && tab_first[s] == (uint32_t)e;
+// First occurrences as a bitmask over entries: bit e is set when entry e
+// is the first of its slot (one pass over the table's slots), so counting
+// and compaction read 1 bit per entry instead of gathering from the table.
+__global__ __launch_bounds__(kBlock) void k_mark_first(const uint32_t* __restrict__ first, int64_t cap,
+                                                       uint32_t* __restrict__ bits) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += stride) {
+    const uint32_t v = first[s];
+    if (v != kNoFirst) atomicOr(&bits[v >> 5], 1u << (v & 31));
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_first(const int32_t* __restrict__ slot,
-                                                        const uint32_t* __restrict__ tab_first,
-                                                        int64_t L, uint32_t* __restrict__ counts) {
+// The first-occurrence flags of entries e0 .. e0 + 7 (e0 a multiple of 8).
+__device__ __forceinline__ uint32_t first_flags(const uint32_t* bits, int64_t e0) {
+  return ((const uint8_t*)bits)[e0 >> 3];
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_first(const uint32_t* __restrict__ bits, int64_t L,
+                                                        uint32_t* __restrict__ counts) {
   const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
-  int c = 0;
-  for (int u = 0; u < kItems; ++u) {
-    const int64_t e = base + u;
-    if (e < L && is_first(slot, tab_first, e)) ++c;
-  }
+  const int c = base < L ? __popc(first_flags(bits, base)) : 0;
   int total;
   (void)block_exclusive_scan(c, &total);
   if (threadIdx.x == 0) counts[blockIdx.x] = (uint32_t)total;
@@ -292,7 +299,8 @@ __device__ __forceinline__ int32_t vertex_coord(const int32_t* pt_r0, const uint
   return pt_r0[i * d + l] + k - ((int)pt_rank[i * d + l] > d - k ? d + 1 : 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact(const int32_t* __restrict__ slot,
+__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ bits,
+                                                    const int32_t* __restrict__ slot,
                                                     uint32_t* __restrict__ tab_first, int64_t L,
                                                     const uint32_t* __restrict__ offsets,
                                                     const int32_t* __restrict__ pt_r0,
@@ -300,18 +308,12 @@ __global__ __launch_bounds__(kBlock) void k_compact(const int32_t* __restrict__ 
                                                     int64_t m, int32_t* __restrict__ keys,
                                                     uint32_t* __restrict__ flags) {
   const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
-  bool flag[kItems];
-  int c = 0;
-  for (int u = 0; u < kItems; ++u) {
-    const int64_t e = base + u;
-    flag[u] = e < L && is_first(slot, tab_first, e);
-    c += flag[u] ? 1 : 0;
-  }
+  const uint32_t fl = base < L ? first_flags(bits, base) : 0u;
   int total;
-  uint32_t pos = offsets[blockIdx.x] + (uint32_t)block_exclusive_scan(c, &total);
+  uint32_t pos = offsets[blockIdx.x] + (uint32_t)block_exclusive_scan(__popc(fl), &total);
   const int D = d + 1;
   for (int u = 0; u < kItems; ++u) {
-    if (!flag[u]) continue;
+    if (!((fl >> u) & 1u)) continue;
     if ((int64_t)pos >= m) {  // the two counting passes disagree: never expected
       atomicOr(flags, BF_COLLISION);
       break;
@@ -394,24 +396,19 @@ __global__ __launch_bounds__(kBlock) void k_point_key(const int32_t* __restrict_
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact_internal(const int32_t* __restrict__ slot_s,
+__global__ __launch_bounds__(kBlock) void k_compact_internal(const uint32_t* __restrict__ bits,
+                                                             const int32_t* __restrict__ slot_s,
                                                              uint32_t* __restrict__ first2, int64_t L,
                                                              const uint32_t* __restrict__ offsets,
                                                              const uint32_t* __restrict__ tab_first,
                                                              int64_t m, int32_t* __restrict__ int2can,
                                                              uint32_t* __restrict__ flags) {
   const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kItems;
-  bool flag[kItems];
-  int c = 0;
-  for (int u = 0; u < kItems; ++u) {
-    const int64_t e = base + u;
-    flag[u] = e < L && is_first(slot_s, first2, e);
-    c += flag[u] ? 1 : 0;
-  }
+  const uint32_t fl = base < L ? first_flags(bits, base) : 0u;
   int total;
-  uint32_t pos = offsets[blockIdx.x] + (uint32_t)block_exclusive_scan(c, &total);
+  uint32_t pos = offsets[blockIdx.x] + (uint32_t)block_exclusive_scan(__popc(fl), &total);
   for (int u = 0; u < kItems; ++u) {
-    if (!flag[u]) continue;
+    if (!((fl >> u) & 1u)) continue;
     if ((int64_t)pos >= m) {
       atomicOr(flags, BF_COLLISION);
       break;
@@ -978,7 +975,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   int rc;
   enum {
     T_R0, T_RANK, T_SLOT, T_TAB, T_FIRST, T_COUNTS, T_OFFS, T_WORDS, T_W, T_NBRC,
-    T_SLOTS, T_FIRST2, T_CAN2INT, T_KA, T_KB, T_VA, T_VB, T_SORTTMP, T_PM, T_SUB, T_ORD, T_CNT
+    T_SLOTS, T_FIRST2, T_CAN2INT, T_KA, T_KB, T_VA, T_VB, T_SORTTMP, T_PM, T_SUB, T_ORD, T_CNT, T_BITS
   };
   if ((rc = tr.alloc(T_R0, sizeof(int32_t) * n * d))) return rc;
   if ((rc = tr.alloc(T_RANK, sizeof(uint8_t) * n * d))) return rc;
@@ -1114,9 +1111,21 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
                        tab_first, first2, (unsigned long long)(cap - 1), hc, maxp, slot, slot_s, words);
     SGP_LAUNCH_CHECK("k_tile_insert");
   }
+  // first-occurrence bitmasks: caller order (canonical numbering), sorted order (first touch)
+  const int64_t nwords_bits = (Lel + 31) / 32;
+  if ((rc = tr.alloc(T_BITS, sizeof(uint32_t) * 2 * nwords_bits))) return rc;
+  uint32_t* bits1 = (uint32_t*)tr.ptr[T_BITS];
+  uint32_t* bits2 = bits1 + nwords_bits;
+  if ((rc = launch_fill_u32(bits1, (size_t)(2 * nwords_bits), 0u, st))) return rc;
   {
     ProfScope ps(KK_COUNT, st);
-    hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel,
+    hipLaunchKernelGGL(k_mark_first, dim3(grid_for(cap, kBlock, 16384)), dim3(kBlock), 0, st,
+                       (const uint32_t*)tab_first, cap, bits1);
+    SGP_LAUNCH_CHECK("k_mark_first");
+    hipLaunchKernelGGL(k_mark_first, dim3(grid_for(cap, kBlock, 16384)), dim3(kBlock), 0, st,
+                       (const uint32_t*)first2, cap, bits2);
+    SGP_LAUNCH_CHECK("k_mark_first");
+    hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, (const uint32_t*)bits1, Lel,
                        counts);
     SGP_LAUNCH_CHECK("k_count_first");
   }
@@ -1158,7 +1167,8 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   int32_t* can2int = (int32_t*)tr.ptr[T_CAN2INT];
   {
     ProfScope ps(KK_COMPACT, st);
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kBlock), 0, st, slot, tab_first, Lel, offs,
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kBlock), 0, st, (const uint32_t*)bits1, slot,
+                       tab_first, Lel, offs,
                        pt_r0, pt_rank, d, m, (int32_t*)L->keys.ptr, words);
     SGP_LAUNCH_CHECK("k_compact");
   }
@@ -1172,7 +1182,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   // ---- internal numbering: lattice points by first touch in sorted order
   {
     ProfScope ps(KK_COUNT, st);
-    hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, slot_s, first2, Lel,
+    hipLaunchKernelGGL(k_count_first, dim3((unsigned)nb), dim3(kBlock), 0, st, (const uint32_t*)bits2, Lel,
                        counts);
     SGP_LAUNCH_CHECK("k_count_first");
   }
@@ -1183,7 +1193,8 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   }
   {
     ProfScope ps(KK_ORDER, st);
-    hipLaunchKernelGGL(k_compact_internal, dim3((unsigned)nb), dim3(kBlock), 0, st, slot_s, first2, Lel,
+    hipLaunchKernelGGL(k_compact_internal, dim3((unsigned)nb), dim3(kBlock), 0, st, (const uint32_t*)bits2,
+                       slot_s, first2, Lel,
                        offs, tab_first, m, (int32_t*)L->int2can.ptr, words);
     SGP_LAUNCH_CHECK("k_compact_internal");
     hipLaunchKernelGGL(k_resolve_internal, dim3(grid_for(Lel, kBlock, 16384)), dim3(kBlock), 0, st,
