@@ -376,13 +376,18 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict_
 // lattice points are then renumbered by first touch in that order, and W^T
 // is stored as a CSR over those numbers so that the splat is a gather.
 
+constexpr int kRankKey = 4;  // most coordinate ranks in the point sort key
+
 struct KeyPack {
   int32_t lo[kMaxD];
   int32_t shift[kMaxD];
   int nk;  // leading dimensions packed into the key
+  int nr;  // ranks of coordinates 0 .. nr-1 packed below them, rb bits each
+  int rb;
 };
 
-__global__ __launch_bounds__(kBlock) void k_point_key(const int32_t* __restrict__ pt_r0, int64_t n, int d,
+__global__ __launch_bounds__(kBlock) void k_point_key(const int32_t* __restrict__ pt_r0,
+                                                      const uint8_t* __restrict__ pt_rank, int64_t n, int d,
                                                       KeyPack kp, unsigned long long* __restrict__ key,
                                                       uint32_t* __restrict__ val) {
   const int D = d + 1;
@@ -391,6 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_point_key(const int32_t* __restrict_
     unsigned long long k = 0;
     for (int l = 0; l < kp.nk; ++l)
       k |= (unsigned long long)(uint32_t)(pt_r0[i * d + l] / D - kp.lo[l]) << kp.shift[l];
+    for (int l = 0; l < kp.nr; ++l)
+      k |= (unsigned long long)pt_rank[i * d + l] << (kp.rb * (kp.nr - 1 - l));
     key[i] = k;
     val[i] = (uint32_t)i;
   }
@@ -1029,7 +1036,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     set_error("lattice_build: |x|/lengthscale too large, a lattice coordinate leaves int32");
     return SGP_EOVERFLOW;
   }
-  // sort key: remainder-0 coordinates, leading dimensions first, as many as fit in 64 bits
+  // sort key: remainder-0 coordinates, leading dimensions first, as many as
+  // fit in 64 bits; when all of them fit, the ranks of the first few
+  // coordinates follow, so that points of one remainder-0 cell are grouped by
+  // simplex and a tile touches fewer distinct lattice points
   KeyPack kp;
   int key_bits = 0;
   {
@@ -1043,6 +1053,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
       used += b;
       nk = l + 1;
     }
+    kp.nr = 0;
+    kp.rb = bits_for((uint64_t)d);
+    if (nk == d) kp.nr = std::min(std::min(d, kRankKey), (64 - used) / kp.rb);
+    used += kp.nr * kp.rb;
     int sh = used;
     for (int l = 0; l < nk; ++l) {
       sh -= bl[l];
@@ -1083,8 +1097,8 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     unsigned long long* kb = (unsigned long long*)tr.ptr[T_KB];
     {
       ProfScope ps(KK_ORDER, st);
-      hipLaunchKernelGGL(k_point_key, dim3(grid_for(n, kBlock, 16384)), dim3(kBlock), 0, st, pt_r0, n,
-                         d, kp, ka, va);
+      hipLaunchKernelGGL(k_point_key, dim3(grid_for(n, kBlock, 16384)), dim3(kBlock), 0, st, pt_r0,
+                         (const uint8_t*)pt_rank, n, d, kp, ka, va);
       SGP_LAUNCH_CHECK("k_point_key");
     }
     bool in_alt = false;

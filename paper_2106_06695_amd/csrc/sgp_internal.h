@@ -142,7 +142,9 @@ struct sgp_lattice {
   int64_t solve_rows = 0;       // CG solves on the first solve_rows points only (0 = all)
 
   // Internal order: points sorted by their remainder-0 lattice point
-  // (lexicographic), lattice points numbered by first touch in that order.
+  // (lexicographic), then by the ranks of their first coordinates (which
+  // groups points of one simplex), lattice points numbered by first touch in
+  // that order.
   // Sorted points are cut into tiles of tile_points consecutive points (the
   // entries of tile t are entries t*P*(d+1) onwards, in both orders); each
   // tile lists the distinct lattice points it touches ("runs"), which the
