@@ -1,12 +1,14 @@
 // Lattice construction (Section 3.2, Splat and Blur):
 //   k_elevate         elevation, enclosing simplex and barycentric weights
 //                     of every point
-//   (points sorted by their remainder-0 lattice point, then in tiles of P
-//   consecutive sorted points)
+//   k_point_key + radix sort
+//                     points sorted by their remainder-0 lattice point, then
+//                     by the ranks of their first coordinates; tiles of P
+//                     consecutive sorted points
 //   k_tile_insert     hash every simplex vertex of a tile, insert each
 //                     distinct one into a hash table once, and keep per slot
 //                     its first entry in caller order and in sorted order
-//   k_count_first / k_scan / k_compact
+//   k_mark_first / k_count_first / k_scan / k_compact
 //                     number the distinct vertices by first occurrence in
 //                     the caller's (point, vertex) order and write their keys
 //   k_neighbors       neighbours of every lattice point along the d+1
@@ -14,8 +16,8 @@
 //   internal numbering by first touch in sorted order, then per tile the
 //   runs (k_tile_order / k_tile_fill) and the pieces grouped by lattice point
 //
-// Hash table: open addressing with linear probing over 64-bit key hashes
-// (a slot is claimed by one 64-bit compare-and-swap, so insertion is
+// Hash table: open addressing with linear probing over 64-bit key hashes,
+// first tried at an eighth of its worst-case size (a slot is claimed by one 64-bit compare-and-swap, so insertion is
 // lock-free and never waits on another lane). Two distinct keys with equal
 // hashes would share a slot; every entry's key is compared with its tile
 // group's first key (k_tile_insert) and every run's key with its lattice
