@@ -19,10 +19,11 @@
 // Hash table: open addressing with linear probing over 64-bit key hashes,
 // first tried at an eighth of its worst-case size (a slot is claimed by one 64-bit compare-and-swap, so insertion is
 // lock-free and never waits on another lane). Two distinct keys with equal
-// hashes would share a slot; every entry's key is compared with its tile
-// group's first key (k_tile_insert) and every run's key with its lattice
-// point's stored key (k_tile_order), and the host rebuilds with a new seed
-// if any differ, so the final lattice is exact.
+// hashes would share a slot; every entry's key is compared with its hashing
+// group's first key (k_tile_insert), and that first key, in every tile that
+// holds the group, with its lattice point's stored key (k_tile_order). The
+// host rebuilds with a new seed if any differ, so the final lattice is
+// exact.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -623,11 +624,12 @@ __device__ inline void tile_ranks(TileSort& T, int ne, int K, TileRanks& r) {
 
 // Pass 1: sort each tile, keep the order (entry within the tile per sorted
 // position) and count its runs and pieces.
-// Each run's key is also compared with its lattice point's canonical key:
-// distinct keys with equal hashes in different tiles share a lattice point,
-// and one of their runs then differs from it.
+// Keys are also compared with their lattice point's canonical key (each
+// run's first entry and each hashing group's first entry in a run):
+// distinct keys with equal hashes in different groups share a lattice
+// point, and one of those entries then differs from it.
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_order(const sgp_entry* __restrict__ pm, int64_t n,
-                                                             int D, int P, int K, int mbits,
+                                                             int D, int P, int K, int mbits, int Pi,
                                                              const uint32_t* __restrict__ perm,
                                                              const int32_t* __restrict__ pt_r0,
                                                              const uint8_t* __restrict__ pt_rank,
@@ -651,10 +653,46 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
   tile_radix(T.key, T.wsum64, mbits);
   TileRanks r;
   tile_ranks(T, ne, K, r);
-  // one thread per run: its first entry's key against the stored key
+  // Positions whose key is compared with the stored key: the first entry of
+  // each run, and within a run the first entry from each hashing group (the
+  // blocks of k_tile_insert hold Pi sorted points and need not line up with
+  // tiles; inside one group every entry already matched its group's first).
+  // The run starts are no longer read, so their array takes the list.
+  // A tile of P <= 3 Pi points meets at most three group starts; gs[]
+  // holds them as entry indices within the tile (past the tile: never met).
+  int gs[3];
+  {
+    const int off = (int)(p0 % Pi);  // points of the tile's first group before the tile
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gs[k] = ((k + 1) * Pi - off) * D;
+  }
+  auto group_of = [&](int e) { return (e >= gs[0] ? 1 : 0) + (e >= gs[1] ? 1 : 0) + (e >= gs[2] ? 1 : 0); };
+  bool ck[kTileSpan];
+  int c = 0;
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u) {
+    const int i = threadIdx.x * kTileSpan + u;
+    ck[u] = false;
+    if (i < ne) {
+      if (r.rs[u]) {
+        ck[u] = true;
+      } else {
+        const int e = (int)(T.key[tile_at(i)] & 4095u);
+        const int ep = (int)(T.key[tile_at(i - 1)] & 4095u);
+        ck[u] = group_of(e) != group_of(ep);
+      }
+    }
+    c += ck[u] ? 1 : 0;
+  }
+  int nchk;
+  int pos = tile_scan(c, T.wsum, &nchk);
+#pragma unroll
+  for (int u = 0; u < kTileSpan; ++u)
+    if (ck[u]) T.rstart[pos++] = threadIdx.x * kTileSpan + u;
+  __syncthreads();
   const int d = D - 1;
   bool bad = false;
-  for (int q = threadIdx.x; q < r.runs; q += kTileThreads) {
+  for (int q = threadIdx.x; q < nchk; q += kTileThreads) {
     const unsigned long long k = T.key[tile_at(T.rstart[q])];
     const unsigned le = (unsigned)(k & 4095u);
     const int64_t pt = perm[p0 + le / (unsigned)D];
@@ -1115,6 +1153,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   // 4, so that every tile's entries start 4-byte aligned in the 8- and
   // 16-bit arrays
   const int P = std::min(256, 4096 / D) & ~3;
+  if (P > 3 * (kInsEntries / D)) {  // k_tile_order follows at most three hashing groups per tile
+    set_error("lattice_build: internal tile shape error (d = %d)", d);
+    return SGP_EINVAL;
+  }
   const int64_t ntiles = (n + P - 1) / P;
   if ((rc = launch_fill_u32((uint32_t*)tab, (size_t)cap * 2, 0u, st))) return rc;
   if ((rc = launch_fill_u32(tab_first, (size_t)cap, kNoFirst, st))) return rc;
@@ -1241,7 +1283,8 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
     {
       ProfScope ps(KK_ORDER, st);
       hipLaunchKernelGGL(k_tile_order, dim3((unsigned)ntiles), dim3(kTileThreads), 0, st,
-                         (const sgp_entry*)tr.ptr[T_PM], n, D, P, kPiece, mb, (const uint32_t*)perm,
+                         (const sgp_entry*)tr.ptr[T_PM], n, D, P, kPiece, mb, kInsEntries / D,
+                         (const uint32_t*)perm,
                          (const int32_t*)pt_r0, (const uint8_t*)pt_rank, (const int32_t*)L->keys.ptr,
                          (const int32_t*)L->int2can.ptr, ord, runs, pieces, words);
       SGP_LAUNCH_CHECK("k_tile_order");
