@@ -374,8 +374,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict_
 
 // ---------------------------------------------------------------------------
 // Internal order. Points are sorted by their remainder-0 lattice point
-// (coordinates in units of d+1, packed most-significant-first into 64 bits)
-// so that a block of consecutive points touches few distinct lattice points;
+// (coordinates in units of d+1, packed most-significant-first into 64 bits,
+// then the ranks of the first coordinates when they fit) so that a block of
+// consecutive points touches few distinct lattice points;
 // lattice points are then renumbered by first touch in that order, and W^T
 // is stored as a CSR over those numbers so that the splat is a gather.
 
