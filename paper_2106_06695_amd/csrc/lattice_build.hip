@@ -17,8 +17,9 @@
 //   runs (k_tile_order / k_tile_fill) and the pieces grouped by lattice point
 //
 // Hash table: open addressing with linear probing over 64-bit key hashes,
-// first tried at an eighth of its worst-case size (a slot is claimed by one 64-bit compare-and-swap, so insertion is
-// lock-free and never waits on another lane). Two distinct keys with equal
+// first tried at an eighth of its worst-case size (a slot is claimed by one
+// 64-bit compare-and-swap, so insertion is lock-free and never waits on
+// another lane). Two distinct keys with equal
 // hashes would share a slot; every entry's key is compared with its hashing
 // group's first key (k_tile_insert), and that first key, in every tile that
 // holds the group, with its lattice point's stored key (k_tile_order). The
