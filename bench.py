@@ -353,7 +353,7 @@ def main(argv=None):
                                "Rademacher probes), noise 0.05, RBF r=1, " + args.blur + " blur, 20 CG iterations",
                    "n": n, "d": d, "C": C, "m": m, "m_over_L": m / (n * (d + 1)),
                    "cg_iterations": iters, "blur": args.blur},
-        "roofline": {"bound": "hbm", "kernel": dom + (" (splat_tile + splat_gather)" if dom == "splat" else ""),
+        "roofline": {"bound": "hbm", "kernel": dom + (" (splat_tile + splat_gather + gather_fix)" if dom == "splat" else ""),
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom),
                      "algo_bytes_per_launch": dom_bytes},
