@@ -297,7 +297,9 @@ def main(argv=None):
             kernels[kind] = {"launches": launches, "total_ms": round(ms, 3), "avg_us": round(avg * 1e3, 2),
                              "algo_GBps": round(b / (avg / 1e3) / 1e9, 1) if b else None}
     # the splat runs as two passes (per-tile reduction, then per-lattice-point
-    # gather of the tile partials); its algorithmic bytes cover both
+    # gather of the tile partials, whose small fix-up kernel for lattice
+    # points spanning several gather ranges is timed with it); its
+    # algorithmic bytes cover all three kernels
     stage_ms = {k: kernels[k]["total_ms"] for k in ("blur", "slice") if k in kernels}
     stage_ms["splat"] = kernels["splat"]["total_ms"] + kernels.get("splat_gather", {"total_ms": 0.0})["total_ms"]
     dom = max(stage_ms, key=stage_ms.get)
