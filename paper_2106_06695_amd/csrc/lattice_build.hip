@@ -109,11 +109,12 @@ struct SimplexArgs {
 constexpr unsigned long long kMaxProbe = 4096;
 constexpr unsigned long long kMaxProbeReduced = 32;
 
-// Read-only lookup; -1 if h is not in the table.
-__device__ int64_t table_find(const unsigned long long* tab, unsigned long long mask,
-                              unsigned long long h, unsigned long long maxp) {
-  unsigned long long s = h & mask;
-  for (unsigned long long probe = 0; probe <= mask && probe < maxp; ++probe) {
+// Read-only lookup. Slot of hash h (-1 if absent), once the first probe (slot s0 = h & mask,
+// which holds another hash) has been read: linear probing from s0 + 1.
+__device__ int64_t table_find_from(const unsigned long long* tab, unsigned long long mask,
+                                   unsigned long long h, unsigned long long maxp, unsigned long long s0) {
+  unsigned long long s = (s0 + 1) & mask;
+  for (unsigned long long probe = 1; probe <= mask && probe < maxp; ++probe) {
     const unsigned long long cur = tab[s];
     if (cur == h) return (int64_t)s;
     if (cur == kEmpty) return -1;
@@ -349,25 +350,45 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const int32_t* __restrict_
     const int k = (int)(g / m);
     const int64_t j = g - (int64_t)k * m;
     const int32_t* kj = keys + j * d;
-    int ti = 0;
-    for (int t = -r; t <= r; ++t) {
-      if (t == 0) continue;
-      unsigned long long h = 0;
-      for (int l = 0; l < d; ++l) h = hash_acc(h, hc.a[l], kj[l] + (l == k ? -t * d : t));
-      h = hash_final(h);
-      int32_t found = -1;
-      const int64_t s = table_find(tab, mask, h, maxp);
-      if (s >= 0) {
-        const uint32_t v = tab_first[s];
-        const int64_t cand = (int64_t)(v & ~kCanonBit);
-        if ((v & kCanonBit) && cand < m) {
+    // offsets -t and +t together, so that the loads of both lookups are in
+    // flight at once
+    for (int t = 1; t <= r; ++t) {
+      unsigned long long h[2] = {0, 0};
+      for (int l = 0; l < d; ++l) {
+        const int32_t c = kj[l];
+        h[0] = hash_acc(h[0], hc.a[l], c + (l == k ? t * d : -t));
+        h[1] = hash_acc(h[1], hc.a[l], c + (l == k ? -t * d : t));
+      }
+      int64_t sl[2];
+      unsigned long long cur[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        h[u] = hash_final(h[u]);
+        sl[u] = (int64_t)(h[u] & mask);
+        cur[u] = tab[sl[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        // the first probe is usually decisive; otherwise keep probing
+        if (cur[u] != h[u])
+          sl[u] = cur[u] == kEmpty ? -1 : table_find_from(tab, mask, h[u], maxp, (unsigned long long)sl[u]);
+      }
+      uint32_t v[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) v[u] = sl[u] >= 0 ? tab_first[sl[u]] : 0u;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int tt = u == 0 ? -t : t;
+        int32_t found = -1;
+        const int64_t cand = (int64_t)(v[u] & ~kCanonBit);
+        if (sl[u] >= 0 && (v[u] & kCanonBit) && cand < m) {
           bool same = true;
-          for (int l = 0; l < d; ++l) same &= keys[cand * d + l] == kj[l] + (l == k ? -t * d : t);
+          for (int l = 0; l < d; ++l) same &= keys[cand * d + l] == kj[l] + (l == k ? -tt * d : tt);
           if (same) found = (int32_t)cand;
         }
+        const int ti = tt < 0 ? tt + r : tt + r - 1;
+        nbr[((int64_t)k * T + ti) * m + j] = found;
       }
-      nbr[((int64_t)k * T + ti) * m + j] = found;
-      ++ti;
     }
   }
 }
