@@ -161,6 +161,23 @@ void lattice_free(sgp_lattice* L);
 /* Message of the last failure on this thread ("" if none). */
 const char* sgp_last_error(void);
 
+/* Device memory from the caller's allocator (process-wide; the interface's
+ * handle on memory management, so that the library's buffers come out of,
+ * e.g., a framework's caching allocator). alloc(bytes, stream) returns device
+ * memory of the current device usable in stream order on `stream` (a
+ * hipStream_t), or NULL on failure (the call then fails with SGP_ENOMEM);
+ * free(ptr, stream) takes back a block that alloc returned, either after
+ * the device has finished every use of it or with `stream` ordering every
+ * use, so a stream-ordered allocator may hand it out again to later work on
+ * that stream. Lattices, build temporaries and gradient work buffers use it;
+ * the library's own idle-block cache is bypassed while it is set. The hooks
+ * are called with a library lock held and must not call the library.
+ * Both NULL restores the built-in stream-ordered pool; one NULL is
+ * SGP_EINVAL. The allocator can change only while the library holds no
+ * device block (every lattice freed): otherwise SGP_EINVAL and nothing
+ * changes. Returns SGP_OK. */
+int sgp_set_allocator(void* (*alloc)(size_t bytes, void* stream), void (*free)(void* ptr, void* stream));
+
 /* CG iterations as HIP graphs (process-wide switch, default on). When on,
  * cg_solve records a block of iterations (4 between convergence polls, 8
  * when tol == 0) into a graph once per call and replays it, which removes

@@ -26,6 +26,7 @@ __all__ = [
     "SGPError", "Lattice", "lattice_build", "lattice_mvm", "cg_solve", "lattice_mvm_grad",
     "lattice_info", "lattice_export", "lattice_free", "lattice_kernel_mvm", "profile",
     "library_path", "cg_graph_enable", "blur_fuse_enable", "autotune", "autotune_reset",
+    "set_allocator", "use_torch_allocator",
 ]
 
 SYMMETRIC, FORWARD, REVERSE = 0, 1, 2
@@ -287,6 +288,48 @@ def autotune(lat: Lattice, C: int, fp64: bool = True, reps: int = 3) -> dict:
 def autotune_reset() -> None:
     """Forget every autotuned launch choice."""
     _check(_lib.load().sgp_autotune_reset())
+
+
+_allocator_hooks = None  # the installed ctypes callbacks, kept alive while set
+
+
+def set_allocator(alloc=None, free=None) -> None:
+    """Take the library's device memory from alloc(nbytes, stream) -> device
+    pointer (int; 0 on failure) and give it back with free(ptr, stream),
+    stream being a hipStream_t as an int; both None restores the built-in
+    pool (sgp_set_allocator). Raises SGPError while a lattice is alive. The
+    hooks must not call into this module's functions."""
+    global _allocator_hooks
+    lib = _lib.load()
+    if (alloc is None) != (free is None):
+        raise ValueError("set_allocator: give both alloc and free, or neither")
+    if alloc is None:
+        _check(lib.sgp_set_allocator(None, None))
+        _allocator_hooks = None
+        return
+
+    def _alloc(nbytes, stream):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0))) or None
+        except Exception:  # a failed allocation is reported by the library
+            return None
+
+    def _free(ptr, stream):
+        free(int(ptr), int(stream or 0))
+
+    hooks = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))
+    _check(lib.sgp_set_allocator(*(ctypes.cast(h, ctypes.c_void_p) for h in hooks)))
+    _allocator_hooks = hooks
+
+
+def use_torch_allocator() -> None:
+    """Take the library's device memory from torch's caching allocator on
+    the current device (it then shows in torch.cuda.memory_allocated)."""
+    import torch
+
+    dev = torch.cuda.current_device()
+    set_allocator(lambda n, s: torch.cuda.caching_allocator_alloc(n, dev, s),
+                  lambda p, s: torch.cuda.caching_allocator_delete(p))
 
 
 class profile:

@@ -17,6 +17,9 @@ class Opts(ctypes.Structure):
 
 # name -> (restype, argtypes), one entry per declaration in include/simplexgp.h
 _P, _I32, _I64, _F, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+# sgp_set_allocator's hooks: alloc(bytes, stream) -> device pointer, free(ptr, stream)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 SIGNATURES = {
     "sgp_opts_default": (None, [_P]),
     "lattice_build": (ctypes.c_int, [_P, _I64, _I32, _P, _P, _P, _P]),
@@ -27,6 +30,7 @@ SIGNATURES = {
     "lattice_export": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "lattice_free": (None, [_P]),
     "sgp_last_error": (ctypes.c_char_p, []),
+    "sgp_set_allocator": (ctypes.c_int, [_P, _P]),  # ALLOC_FN / FREE_FN pointers, or NULL
     "sgp_cg_graph_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_blur_fuse_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,

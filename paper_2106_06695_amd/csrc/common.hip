@@ -53,6 +53,33 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
   return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
 }
 
+// Device memory comes from the library's stream-ordered pool, or from a
+// caller's allocator (sgp_set_allocator). Every block is returned to the
+// allocator it came from: the allocator changes only while the library
+// holds no block (g_live counts blocks held by lattices, temporaries and
+// the gradient, not idle cached ones). The hooks run under g_alloc_mu.
+namespace {
+std::mutex g_alloc_mu;
+void* (*g_user_alloc)(size_t, void*) = nullptr;
+void (*g_user_free)(void*, void*) = nullptr;
+int64_t g_live = 0;
+}  // namespace
+
+bool user_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_user_alloc != nullptr;
+}
+
+void dev_release(void* p, hipStream_t s) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  --g_live;
+  if (g_user_free)
+    g_user_free(p, (void*)s);
+  else
+    (void)hipFreeAsync(p, s);
+}
+
 // Idle device blocks kept for reuse, per device, up to a quarter of the
 // device memory. Freeing pool memory costs the host about 0.2 ms per block
 // on this runtime, so a lattice's ~20 arrays are recycled instead.
@@ -72,6 +99,8 @@ BlockCache* block_cache() {
 }  // namespace
 
 void* block_take(size_t bytes, size_t* cap) {
+  std::lock_guard<std::mutex> la(g_alloc_mu);
+  if (g_user_alloc) return nullptr;  // the caller's allocator does its own caching
   BlockCache* c = block_cache();
   if (!c) return nullptr;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -81,26 +110,53 @@ void* block_take(size_t bytes, size_t* cap) {
   *cap = it->first;
   c->bytes -= it->first;
   c->blocks.erase(it);
+  ++g_live;
   return p;
 }
 
 void block_give(void* p, size_t cap) {
   if (!p) return;
-  BlockCache* c = block_cache();
-  if (c) {
-    std::lock_guard<std::mutex> lk(c->mu);
-    if (!c->limit) {
-      size_t fr = 0, total = 0;
-      c->limit = hipMemGetInfo(&fr, &total) == hipSuccess ? total / 4 : ((size_t)1 << 32);
-    }
-    if (c->bytes + cap <= c->limit) {
-      c->blocks.emplace(cap, p);
-      c->bytes += cap;
-      return;
+  {
+    std::lock_guard<std::mutex> la(g_alloc_mu);
+    BlockCache* c = g_user_alloc ? nullptr : block_cache();
+    if (c) {
+      std::lock_guard<std::mutex> lk(c->mu);
+      if (!c->limit) {
+        size_t fr = 0, total = 0;
+        c->limit = hipMemGetInfo(&fr, &total) == hipSuccess ? total / 4 : ((size_t)1 << 32);
+      }
+      if (c->bytes + cap <= c->limit) {
+        c->blocks.emplace(cap, p);
+        c->bytes += cap;
+        --g_live;
+        return;
+      }
     }
   }
-  (void)hipFreeAsync(p, lib_stream());
+  dev_release(p, lib_stream());
 }
+
+// Release every idle cached block of every device (before the allocator
+// changes). g_alloc_mu is held by the caller.
+namespace {
+void flush_block_caches() {
+  int ndev = 0, cur = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hipGetDevice(&cur) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  for (int dev = 0; dev < ndev && dev < 64; ++dev) {
+    if (hipSetDevice(dev) != hipSuccess) continue;
+    BlockCache* c = block_cache();
+    if (!c) continue;
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (auto& kv : c->blocks) (void)hipFreeAsync(kv.second, lib_stream());
+    c->blocks.clear();
+    c->bytes = 0;
+  }
+  (void)hipSetDevice(cur);
+}
+}  // namespace
 
 int dev_alloc(DevBuf& b, size_t bytes, hipStream_t s) {
   b.ptr = nullptr;
@@ -154,9 +210,17 @@ hipMemPool_t lib_pool() {
 }
 
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (g_user_alloc) {
+    *p = g_user_alloc(bytes, (void*)s);
+    if (!*p) return hipErrorOutOfMemory;
+    ++g_live;
+    return hipSuccess;
+  }
   hipMemPool_t pool = lib_pool();
-  if (!pool) return hipMallocAsync(p, bytes, s);
-  return hipMallocFromPoolAsync(p, bytes, pool, s);
+  const hipError_t e = pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMallocAsync(p, bytes, s);
+  if (e == hipSuccess) ++g_live;
+  return e;
 }
 
 hipStream_t lib_stream() {
@@ -375,6 +439,24 @@ void sgp_opts_default(sgp_opts* o) {
 }
 
 const char* sgp_last_error(void) { return g_err; }
+
+int sgp_set_allocator(void* (*alloc)(size_t bytes, void* stream), void (*free_fn)(void* ptr, void* stream)) {
+  using namespace sgp;
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    set_error("sgp_set_allocator: give both functions, or neither for the built-in pool");
+    return SGP_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (g_live != 0) {
+    set_error("sgp_set_allocator: %lld device blocks of the current allocator are still held; "
+              "free every lattice first", (long long)g_live);
+    return SGP_EINVAL;
+  }
+  if (alloc && !g_user_alloc) flush_block_caches();  // idle pool blocks stay with the pool
+  g_user_alloc = alloc;
+  g_user_free = free_fn;
+  return SGP_OK;
+}
 
 int lattice_info(const sgp_lattice* L, int64_t* n, int32_t* d, int64_t* m, int64_t* device_bytes) {
   if (!L) {

@@ -149,7 +149,7 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
     hipStream_t s;
     ~Guard() {
       for (int k = 0; k < 4; ++k)
-        if (b[k]) (void)hipFreeAsync(b[k], s);
+        if (b[k]) dev_release(b[k], s);
     }
   } guard{bufs, s};
   const size_t sizes[4] = {sizeof(double) * n * CH, sizeof(double) * n * CH, sizeof(double) * n * d,

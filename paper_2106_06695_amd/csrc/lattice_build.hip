@@ -1004,7 +1004,7 @@ struct Transient {
       if (idle)
         block_give(ptr[i], cap[i]);
       else
-        (void)hipFreeAsync(ptr[i], s);
+        dev_release(ptr[i], s);
     }
   }
 };

@@ -106,8 +106,12 @@ void dev_free(DevBuf& b);
 void block_give(void* p, size_t cap);
 void* block_take(size_t bytes, size_t* cap);
 hipStream_t lib_stream();
-// Stream-ordered allocation from the library's pool on the current device.
+// Stream-ordered allocation on the current device: from the caller's
+// allocator when one is set (sgp_set_allocator), else from the library's
+// pool. dev_release returns such a block to the allocator it came from, in
+// stream order on s (or at once if the device is done with it).
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_release(void* p, hipStream_t s);
 // Pinned host scratch of at least `bytes` (<= 64 KiB), one per host thread.
 void* pinned_scratch(size_t bytes);
 

@@ -129,3 +129,11 @@ def test_ws3p_scale_matches_paper_sparsity():
     assert abs(rec["target"] - target) < 1e-12
     assert abs(rec["m_over_L"] - target) <= 0.005 * target
     assert 0.5 < rec["scale"] < 1.0 and workloads.ws3p_scale() == rec["scale"]
+
+
+def test_set_allocator_needs_both_hooks(lib):
+    from paper_2106_06695_amd import _lib
+    hook = _lib.ALLOC_FN(lambda n, s: None)
+    assert lib.sgp_set_allocator(ctypes.cast(hook, ctypes.c_void_p), None) == -1  # SGP_EINVAL
+    assert b"both" in lib.sgp_last_error()
+    assert lib.sgp_set_allocator(None, None) == 0  # the built-in pool, nothing held
