@@ -141,6 +141,60 @@ def cpu_baseline(w, n_sample: int, iters: int):
                       f"CG iterations per column (fp64, single thread), {dt:.2f} s"}
 
 
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline_all_cores(w, n_sample: int, iters: int):
+    """The same oracle work spread over the host: one single-threaded oracle
+    process per column (python -m oracle cg: build + iters CG iterations on
+    that column), as many at once as there are cores (at most 16)."""
+    import subprocess
+    import tempfile
+
+    model, ncpu = _host_cpu()
+    C = w.values.shape[1]
+    procs = max(1, min(C, ncpu, 16))
+    with tempfile.TemporaryDirectory() as td:
+        np.save(os.path.join(td, "X.npy"), w.X[:n_sample])
+        np.save(os.path.join(td, "ell.npy"), np.asarray(w.lengthscales, dtype=np.float64))
+        for c in range(C):
+            np.save(os.path.join(td, f"v{c}.npy"), w.values[:n_sample, c:c + 1].astype(np.float64))
+
+        def launch(c):
+            return subprocess.Popen(
+                [sys.executable, "-m", "oracle", "cg", "--X", os.path.join(td, "X.npy"),
+                 "--ell", os.path.join(td, "ell.npy"), "--values", os.path.join(td, f"v{c}.npy"),
+                 "--noise", repr(float(w.noise)), "--tol", "0", "--max-iter", str(iters),
+                 "--out", os.path.join(td, f"x{c}.npy")],
+                cwd=ROOT, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
+
+        t0 = time.perf_counter()
+        pending, running = list(range(C)), []
+        while pending or running:
+            while pending and len(running) < procs:
+                running.append(launch(pending.pop(0)))
+            done = running.pop(0)
+            _, err = done.communicate()
+            if done.returncode != 0:
+                raise RuntimeError(f"oracle process failed: {err.decode()[-400:]}")
+        dt = time.perf_counter() - t0
+    return {"value": n_sample * C * iters / dt, "unit": "points*ch/s", "cores": procs,
+            "kind": "oracle, one single-threaded process per column",
+            "host": f"{model}, {ncpu} cores available",
+            "sample": f"first {n_sample} of {w.n} points, {C} columns: per column an oracle build + "
+                      f"{iters} CG iterations (fp64), {dt:.2f} s wall"}
+
+
 def serving_bench(workers: int, count: int, rhos=(0.5, 0.9, 1.5), seed: int = 1005):
     """Served solves (predictive means) at Poisson arrival rates rho / T, with
     T the mean one-at-a-time service time measured first: p50/p99 latency
@@ -375,6 +429,7 @@ def main(argv=None):
         line["serving"] = serving_bench(args.serve_workers, args.serve)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n), iters)
+        line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(w, min(args.cpu_sample, n), iters)
     print(json.dumps(line), flush=True)
     return 0
 
