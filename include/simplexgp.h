@@ -50,7 +50,8 @@ enum sgp_status {
   SGP_ENOMEM = -2,    /* device or host allocation failed */
   SGP_EOVERFLOW = -3, /* a lattice coordinate leaves int32 (|x|/l too large) */
   SGP_EHIP = -4,      /* HIP runtime error */
-  SGP_EHASH = -5      /* lattice hash table failed to verify after retries */
+  SGP_EHASH = -5      /* lattice hash table full at its largest size, or its
+                         key check failed for 4 seeds */
 };
 
 /* Blur order over the d+1 lattice directions (Section 3.2, Blur). The
