@@ -442,19 +442,25 @@ __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restri
   }
 }
 
-// Lattice points whose rows span several ranges: their fragments in order.
-__global__ __launch_bounds__(kBlock) void k_gather_fix(const int32_t* __restrict__ occ_ptr,
+// Lattice points whose rows span several ranges: each is summed from its
+// fragments in range order by the range its rows end in (one thread per
+// (range, channel); a range's first row belongs to the lattice point that
+// may continue into it).
+__global__ __launch_bounds__(kBlock) void k_gather_fix(const int32_t* __restrict__ row_vert,
+                                                       const int32_t* __restrict__ occ_ptr,
                                                        const void* __restrict__ frag_v,
-                                                       void* __restrict__ U_v, int64_t m, int C,
+                                                       void* __restrict__ U_v, int64_t ngroups, int C,
                                                        int elem) {
-  const int64_t total = m * C;
+  const int64_t total = ngroups * C;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
-    const int64_t j = q / C;
-    const int c = (int)(q - j * C);
+    const int64_t g1 = q / C;
+    const int c = (int)(q - g1 * C);
+    if (g1 == 0) continue;
+    const int64_t j = row_vert[g1 * kGatherRows];
     const int64_t js = occ_ptr[j], je = occ_ptr[j + 1];
-    const int64_t g0 = js / kGatherRows, g1 = (je - 1) / kGatherRows;
-    if (g0 == g1) continue;
+    const int64_t g0 = js / kGatherRows;
+    if (g0 == g1 || (je - 1) / kGatherRows != g1) continue;  // starts here, or ends further on
     const int64_t first = (g0 * 2 + (js == g0 * kGatherRows ? 0 : 1)) * C + c;
     if (elem == 8) {
       const double* frag = (const double*)frag_v;
@@ -1121,8 +1127,9 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
     hipLaunchKernelGGL((k_splat_gather<TU, G>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
                        (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups);
     SGP_LAUNCH_CHECK("k_splat_gather");
-    hipLaunchKernelGGL(k_gather_fix, dim3(grid_cap(m * C)), dim3(kBlock), 0, s,
-                       (const int32_t*)L->occ_ptr.ptr, (const void*)frag, (void*)U0, m, C, (int)sizeof(TU));
+    hipLaunchKernelGGL(k_gather_fix, dim3(grid_cap(ngroups * C)), dim3(kBlock), 0, s,
+                       (const int32_t*)L->row_vert.ptr, (const int32_t*)L->occ_ptr.ptr, (const void*)frag,
+                       (void*)U0, ngroups, C, (int)sizeof(TU));
     SGP_LAUNCH_CHECK("k_gather_fix");
   }
 
