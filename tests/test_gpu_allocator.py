@@ -81,3 +81,27 @@ def test_user_allocator_matches_pool(sgp):
     lat.free()
     for a, b in zip(ref, again):
         np.testing.assert_array_equal(a, b)
+
+
+def test_use_torch_allocator_shows_in_torch(sgp):
+    import torch
+    print("allocator: use_torch_allocator, n=20000 d=6", flush=True)
+    w = workloads.small_case(78, 20000, 6, channels=2, kind="mixture")
+    X, V = _cuda(w.X), _cuda(w.values)
+    gc.collect()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    sgp.use_torch_allocator()
+    try:
+        lat = sgp.lattice_build(X, w.lengthscales)
+        sgp.lattice_mvm(lat, V)
+        torch.cuda.synchronize()
+        held = sgp.lattice_info(lat)["device_bytes"]
+        assert torch.cuda.memory_allocated() - base >= held > 0
+        lat.free()
+        del lat
+        torch.cuda.synchronize()
+    finally:
+        gc.collect()
+        sgp.set_allocator(None, None)
+    assert torch.cuda.memory_allocated() == base
