@@ -585,6 +585,7 @@ struct Blur2Args {
   int C;
   int chains;
   int sum_out;
+  int split;  // two chains with outputs of their own: the grid's halves take one each
   int vec;
   int64_t rows_per_block;
   TU st[3];
@@ -684,6 +685,37 @@ __global__ __launch_bounds__(kBlock) void k_blur2(Blur2Args<TU> a) {
 #pragma unroll
         for (int i = 0; i < VW; ++i)
           if (c + i < a.C) o0[i] = f[i];
+      }
+    }
+  }
+}
+
+// k_blur2 for two chains that write outputs of their own: the grid's first
+// half takes chain 0 and its second half chain 1, the same rows each, so a
+// thread waits on half as many dependent loads.
+template <typename TU, int G>
+__global__ __launch_bounds__(kBlock) void k_blur2_split(Blur2Args<TU> a) {
+  constexpr int VW = blur_vw<G>();
+  constexpr int LPR = G / VW;
+  constexpr int R = kBlock / LPR;
+  const int sub = threadIdx.x % LPR;
+  const unsigned nb = gridDim.x / 2;
+  const int chain = blockIdx.x >= nb ? 1 : 0;
+  const unsigned bid = blockIdx.x - chain * nb;
+  const int64_t j0 = xcd_block(bid, nb) * a.rows_per_block;
+  const int64_t j1 = j0 + a.rows_per_block < a.m ? j0 + a.rows_per_block : a.m;
+  for (int64_t j = j0 + threadIdx.x / LPR; j < j1; j += R) {
+    for (int c = sub * VW; c < a.C; c += G) {
+      const bool vec = a.vec && c + VW <= a.C;
+      TU f[VW];
+      blur2_rows<TU, VW>(a.in[chain], a.nbr1[chain], a.nbr2[chain], a.m, j, a.C, c, a.st, vec, f);
+      TU* o = a.out[chain] + j * a.C + c;
+      if (vec) {
+        write_row<TU, VW>(o, f);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VW; ++i)
+          if (c + i < a.C) o[i] = f[i];
       }
     }
   }
@@ -1171,12 +1203,16 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
       b2.C = C;
       b2.chains = a.chains;
       b2.sum_out = (sym && step + 1 == d) ? 1 : 0;
+      b2.split = (a.chains == 2 && !b2.sum_out) ? 1 : 0;
       b2.vec = a.vec;
       b2.rows_per_block = a.rows_per_block;
       for (int t = 0; t < 3; ++t) b2.st[t] = a.st[t];
       {
         ProfScope ps(KK_BLUR, s);
-        hipLaunchKernelGGL((k_blur2<TU, G>), dim3(bblocks), dim3(kBlock), 0, s, b2);
+        if (b2.split)
+          hipLaunchKernelGGL((k_blur2_split<TU, G>), dim3(2 * bblocks), dim3(kBlock), 0, s, b2);
+        else
+          hipLaunchKernelGGL((k_blur2<TU, G>), dim3(bblocks), dim3(kBlock), 0, s, b2);
         SGP_LAUNCH_CHECK("k_blur2");
       }
       step += 2;
