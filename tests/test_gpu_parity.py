@@ -105,6 +105,19 @@ def test_structure_ties_and_duplicates(sgp, orc):
     _assert_structure(sgp, lat, olat)
 
 
+@pytest.mark.parametrize("spread,seed", [(60.0, 5), (8.0, 6), (10.0, 6)])
+def test_structure_point_key_widths(sgp, orc, spread, seed):
+    """Point sort keys of every layout: at d = 12, x ~ U[-spread, spread]
+    needs 86 coordinate bits (only the leading coordinates fit, no ranks;
+    every vertex distinct, so the first hash table fills and grows), 51
+    (three ranks fit) or 57 (one rank)."""
+    _note(f"structure point key spread={spread}")
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-spread, spread, size=(3000, 12)).astype(np.float32)
+    lat, olat = _build_both(sgp, orc, X, np.ones(12))
+    _assert_structure(sgp, lat, olat)
+
+
 def test_structure_matern(sgp, orc):
     _note("structure matern32")
     w = workloads.small_case(21, 1500, 6, kind="mixture")
