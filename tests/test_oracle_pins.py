@@ -179,6 +179,61 @@ def test_ties_zero_rows_and_grid_points(orc):
     assert np.all(bary >= 0) and np.allclose(bary.sum(1), 1)
 
 
+# Exact residual ties at d >= 2. Zero input coordinates make elevated
+# coordinates exactly equal: x = (t, 0, 0) elevates to y = (c, -c, 0, 0) and
+# x = (0, t) to y = (c, c, -2c), where c = t sqrt(d(d+1)) / (s sqrt(j(j+1)))
+# for the nonzero coordinate j and unit lengthscales (the triangular basis of
+# the elevation, scaled so that one lattice step spans s lengthscales;
+# Section 3.2, Splat). The tie rule (ties
+# ranked by lower coordinate index first, rounding half to even) then fixes
+# which vertex of the shared face the point's zero-weight vertex is. The
+# vertices below were worked out by hand from eq. canon_simplex:
+#  (a) d=3, c ~ 1.2: r0 = 0, residuals (c, -c, 0, 0), ranks (0, 3, 1, 2);
+#      vertex k = r0 + k - (d+1) [rank > d-k]: (0,0,0,0), (1,-3,1,1),
+#      (2,-2,2,-2), (3,-1,-1,-1); weights (1 - c/2, c/4, 0, c/4). The
+#      opposite tie order would give vertex 2 = (2,-2,-2,2).
+#  (b) d=2, c ~ 0.5: r0 = 0, residuals (c, c, -2c), ranks (0, 1, 2);
+#      vertices (0,0,0), (1,1,-2), (2,-1,-1); weights (1 - c, c, 0). The
+#      opposite order gives vertex 2 = (-1,2,-1).
+#  (c) d=2, c ~ 1.6: rounding y/3 gives (1, 1, -1), so r0 = (3, 3, -3) with
+#      excess 1; residuals (c-3, c-3, 3-2c) rank (1, 2, 0) before the sum
+#      fix, which lowers the coordinate of rank 2 (index 1): r0 = (3, 0, -3),
+#      ranks (2, 0, 1); vertices (3,0,-3), (1,1,-2), (2,2,-4); vertex 0 has
+#      weight 1 + (c-3)/3 - c/3 = 0 (up to one rounding of the residuals).
+#      The opposite order lowers index 0 instead and gives vertex 0 =
+#      (0,3,-3).
+TIE_CASES = [
+    (3, (1.2, 0.0, 0.0), [[0, 0, 0], [1, -3, 1], [2, -2, 2], [3, -1, -1]], 2),
+    (2, (0.0, 0.5), [[0, 0], [1, 1], [2, -1]], 2),
+    (2, (0.0, 1.6), [[3, 0], [1, 1], [2, 2]], 0),
+]
+
+
+@pytest.mark.parametrize("d,c,expected,zero_vertex", TIE_CASES)
+def test_exact_ties_at_higher_dimension(orc, d, c, expected, zero_vertex):
+    s, _, _, _ = orc.constants(d, 1, orc.RBF)
+    j = np.arange(1, d + 1)
+    x = (np.asarray(c) * s * np.sqrt(j * (j + 1)) / np.sqrt(d * (d + 1))).astype(np.float32)[None, :]
+    y = orc.embed(x, np.ones(d))[0]
+    cval = y[0]
+    assert abs(cval - max(c)) < 1e-6
+    # the zero coordinates produce exact ties in the elevated point
+    if d == 3:
+        assert y[2] == 0.0 and y[3] == 0.0 and y[0] == -y[1]
+    else:
+        assert y[0] == y[1] and y[2] == -2 * y[0]
+    keys, bary, r0, rank = orc.simplex(x, np.ones(d))
+    np.testing.assert_array_equal(keys[0], np.asarray(expected, dtype=np.int32))
+    assert abs(bary[0, zero_vertex]) <= 1e-15
+    assert np.all(bary[0] >= -1e-15) and abs(bary[0].sum() - 1.0) < 1e-12
+    full = _full_keys(r0, rank, d)[0].astype(np.float64)
+    np.testing.assert_allclose(bary[0] @ full, y, atol=1e-12)
+    # the same points inside a lattice: the zero-weight vertex is inserted
+    # (it counts in m), as a vertex of its own
+    lat = orc.Lattice(x, np.ones(d))
+    assert lat.m == d + 1
+
+
 # ---------------------------------------------------------------------------
 # d = 1: the lattice is a grid of spacing s*l, W is linear interpolation and
 # both blur directions are the same 1-D stencil (Section 3.2; Section 4.1).
