@@ -99,7 +99,9 @@ def test_mll_gradient_step_parity(sgp, orc):
 
 def test_mll_gradient_ws4_full(sgp):
     """The differentiation workload at full size: n = 1,000,000, d = 16, 8
-    columns. Checked for completion, finiteness and the adjoint's symmetry."""
+    columns, through the whole gradient step (batched CG, then one adjoint
+    call). Checked for completion and finiteness here; the adjoint's values
+    at this size are compared with the oracle's in test_ws4_full_oracle."""
     from paper_2106_06695_amd import gp
     print("mll gradient ws4 full", flush=True)
     w = workloads.ws4()
