@@ -140,12 +140,20 @@ int lattice_mvm_grad(const sgp_lattice* L, const float* X, const float* V, const
                      int32_t C, float* dX, double* dlogell /* host */, void* stream);
 
 /* Sizes of a built lattice (host outputs, any may be NULL): n, d, the
- * number m of lattice points (m <= n(d+1), Section 5.2) and the device
- * bytes the handle holds. */
+ * number m of lattice points (m <= n(d+1); the lattice-size table of
+ * Section 5.2 reports m for the paper's datasets) and the device bytes the
+ * handle holds. */
 int lattice_info(const sgp_lattice* L, int64_t* n, int32_t* d, int64_t* m,
                  int64_t* device_bytes);
 
-/* Copy the lattice structure to HOST arrays (any may be NULL):
+/* Copy the lattice structure to HOST arrays (any may be NULL): the lattice
+ * points generated by the splat and the enclosing simplex of every point
+ * (Section 3.2, Splat; a vertex k of a point's simplex is its remainder-0
+ * lattice point plus the canonical simplex vertex s_k permuted by the ranks
+ * of the residuals, eq. canon_simplex), and the blur's neighbour table
+ * (Section 3.2, Blur). Lattice points are numbered by first occurrence in
+ * the (point, vertex) row-major scan, which makes the export independent of
+ * the hash table and of the internal order.
  *   keys m x d      int32  first d coordinates of each lattice point
  *                          (the last is minus their sum)
  *   idx  n x (d+1)  int32  lattice point of vertex k of point i's simplex
@@ -178,6 +186,19 @@ const char* sgp_last_error(void);
  * device block (every lattice freed): otherwise SGP_EINVAL and nothing
  * changes. Returns SGP_OK. */
 int sgp_set_allocator(void* (*alloc)(size_t bytes, void* stream), void (*free)(void* ptr, void* stream));
+
+/* The library's idle-block cache on the current device (host outputs, may
+ * be NULL): bytes and blocks of device memory freed by lattices and kept for
+ * reuse (at most a quarter of the device memory). When an allocation from
+ * the built-in pool runs out of memory, the cache is first returned to the
+ * pool and the allocation tried once more, so cached blocks never cause
+ * SGP_ENOMEM. Returns SGP_OK. */
+int sgp_cache_info(int64_t* bytes, int32_t* blocks);
+
+/* Test hook for the out-of-memory path: the next `count` allocations from
+ * the built-in pool (on any device) report out-of-memory without asking the
+ * device. 0 cancels. Returns SGP_OK. */
+int sgp_debug_inject_oom(int32_t count);
 
 /* CG iterations as HIP graphs (process-wide switch, default on). When on,
  * cg_solve records a block of iterations (4 between convergence polls, 8

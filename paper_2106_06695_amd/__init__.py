@@ -260,6 +260,18 @@ def lattice_free(lat: Lattice):
     lat.free()
 
 
+def cache_info() -> dict:
+    """Bytes and blocks in the library's idle-block cache (current device)."""
+    b, k = ctypes.c_int64(), ctypes.c_int32()
+    _check(_lib.load().sgp_cache_info(ctypes.byref(b), ctypes.byref(k)))
+    return {"bytes": int(b.value), "blocks": int(k.value)}
+
+
+def debug_inject_oom(count: int) -> None:
+    """Test hook: the next `count` pool allocations report out-of-memory."""
+    _check(_lib.load().sgp_debug_inject_oom(int(count)))
+
+
 def cg_graph_enable(on: bool) -> bool:
     """Turn graph replay of CG iterations on or off (process-wide); returns
     the previous setting. Results do not depend on it."""

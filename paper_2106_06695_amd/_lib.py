@@ -31,6 +31,8 @@ SIGNATURES = {
     "lattice_free": (None, [_P]),
     "sgp_last_error": (ctypes.c_char_p, []),
     "sgp_set_allocator": (ctypes.c_int, [_P, _P]),  # ALLOC_FN / FREE_FN pointers, or NULL
+    "sgp_cache_info": (ctypes.c_int, [_P, _P]),
+    "sgp_debug_inject_oom": (ctypes.c_int, [_I32]),
     "sgp_cg_graph_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_blur_fuse_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,

@@ -158,6 +158,44 @@ void flush_block_caches() {
 }
 }  // namespace
 
+// Release this device's idle cached blocks to the pool and wait until the
+// pool can hand their memory out again (on any stream). Returns the bytes
+// released.
+namespace {
+size_t flush_idle_blocks() {
+  BlockCache* c = block_cache();
+  if (!c) return 0;
+  size_t freed = 0;
+  {
+    std::lock_guard<std::mutex> la(g_alloc_mu);
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (auto& kv : c->blocks) (void)hipFreeAsync(kv.second, lib_stream());
+    freed = c->bytes;
+    c->blocks.clear();
+    c->bytes = 0;
+  }
+  if (freed) (void)hipStreamSynchronize(lib_stream());
+  (void)hipGetLastError();
+  return freed;
+}
+std::atomic<int> g_inject_oom{0};
+}  // namespace
+
+void inject_oom(int count) { g_inject_oom.store(count > 0 ? count : 0); }
+
+void idle_cache_info(int64_t* bytes, int32_t* blocks) {
+  BlockCache* c = block_cache();
+  int64_t b = 0;
+  int32_t k = 0;
+  if (c) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    b = (int64_t)c->bytes;
+    k = (int32_t)c->blocks.size();
+  }
+  if (bytes) *bytes = b;
+  if (blocks) *blocks = k;
+}
+
 int dev_alloc(DevBuf& b, size_t bytes, hipStream_t s) {
   b.ptr = nullptr;
   b.bytes = 0;
@@ -209,8 +247,16 @@ hipMemPool_t lib_pool() {
   return pools[dev];
 }
 
-hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
+namespace {
+hipError_t pool_alloc_once(void** p, size_t bytes, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (!g_user_alloc) {
+    // test hook: report out-of-memory without asking the pool
+    int left = g_inject_oom.load();
+    while (left > 0 && !g_inject_oom.compare_exchange_weak(left, left - 1)) {
+    }
+    if (left > 0) return hipErrorOutOfMemory;
+  }
   if (g_user_alloc) {
     *p = g_user_alloc(bytes, (void*)s);
     if (!*p) return hipErrorOutOfMemory;
@@ -220,6 +266,18 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
   hipMemPool_t pool = lib_pool();
   const hipError_t e = pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMallocAsync(p, bytes, s);
   if (e == hipSuccess) ++g_live;
+  return e;
+}
+}  // namespace
+
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
+  hipError_t e = pool_alloc_once(p, bytes, s);
+  // Out of memory while idle blocks of other sizes sit in the cache: give
+  // them back to the pool and try once more.
+  if (e == hipErrorOutOfMemory && !user_allocator()) {
+    (void)hipGetLastError();
+    if (flush_idle_blocks() > 0) e = pool_alloc_once(p, bytes, s);
+  }
   return e;
 }
 
@@ -542,6 +600,16 @@ void lattice_free(sgp_lattice* L) {
   delete L;
 }
 
+
+int sgp_cache_info(int64_t* bytes, int32_t* blocks) {
+  sgp::idle_cache_info(bytes, blocks);
+  return SGP_OK;
+}
+
+int sgp_debug_inject_oom(int32_t count) {
+  sgp::inject_oom(count);
+  return SGP_OK;
+}
 
 int sgp_cg_graph_enable(int on) { return g_cg_graph.exchange(on != 0 ? 1 : 0); }
 int sgp_blur_fuse_enable(int on) { return g_blur_fuse.exchange(on != 0 ? 1 : 0); }

@@ -105,3 +105,41 @@ def test_use_torch_allocator_shows_in_torch(sgp):
         gc.collect()
         sgp.set_allocator(None, None)
     assert torch.cuda.memory_allocated() == base
+
+
+def test_out_of_memory_flushes_idle_cache_and_retries(sgp):
+    """An allocation from the built-in pool that runs out of memory returns
+    the idle-block cache to the pool and tries once more: one injected
+    failure is absorbed (results bitwise as without it), two surface as
+    SGP_ENOMEM, and the library stays usable."""
+    print("allocator: out-of-memory retry", flush=True)
+    w = workloads.small_case(78, 5000, 4, channels=3, kind="mixture")
+    G = np.random.default_rng(8).standard_normal(w.values.shape).astype(np.float32)
+    lat, ref = _run(sgp, w, G)
+    lat.free()
+    # the freed lattice's blocks are idle in the cache now
+    assert sgp.cache_info()["blocks"] > 0
+    # a build of another size misses the cache, hits the injected failure,
+    # flushes the cache and succeeds on the retry
+    other = workloads.small_case(79, 40000, 6, channels=1, kind="mixture")
+    sgp.debug_inject_oom(1)
+    try:
+        lat2 = sgp.lattice_build(_cuda(other.X), other.lengthscales)
+    finally:
+        sgp.debug_inject_oom(0)
+    assert lat2.m > 0
+    lat2.free()
+    # both attempts fail: the error is reported, nothing leaks
+    lat, _ = _run(sgp, w, G)
+    lat.free()
+    sgp.debug_inject_oom(2)
+    try:
+        with pytest.raises(sgp.SGPError) as ei:
+            sgp.lattice_build(_cuda(other.X), other.lengthscales)
+        assert ei.value.code == -2
+    finally:
+        sgp.debug_inject_oom(0)
+    lat, got = _run(sgp, w, G)
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a, b)
+    lat.free()
