@@ -139,7 +139,10 @@ class Server:
             self._cv.notify_all()
 
     # -- one request -----------------------------------------------------------
-    def _serve_one(self, req, reserved: int, stream):
+    def _serve_one(self, req, slot: dict, stream):
+        """Serve one request; slot["reserved"] always holds the bytes this
+        request has reserved, so the worker releases exactly that amount
+        whether the request finishes or fails."""
         import torch
         admitted = time.perf_counter() - self._t0
         n, d = req.X.shape
@@ -156,9 +159,9 @@ class Server:
             lat = lattice_build(X_all, req.lengthscales, outputscale=outputscale, solve_rows=n)
             try:
                 actual = int(lattice_info(lat)["device_bytes"]) + solve_bytes(N, C, d, lat.m)
-                if actual < reserved:
-                    self._adjust(reserved, actual)
-                    reserved = actual
+                if actual < slot["reserved"]:
+                    self._adjust(slot["reserved"], actual)
+                    slot["reserved"] = actual
                 A, iters, rel = cg_solve(lat, B, req.noise, req.tol, max_iter=max_iter)
                 a = torch.zeros((N, 1), dtype=torch.float32, device=dev)
                 a[:n] = A[:n, :1]
@@ -168,7 +171,7 @@ class Server:
                 lat.free()
         done = time.perf_counter() - self._t0
         return SolveResult(req.rid, mu, alpha, np.asarray(iters), np.asarray(rel), req.arrival_s,
-                           admitted, done, reserved, actual)
+                           admitted, done, slot["reserved"], actual)
 
     def _worker(self):
         import torch
@@ -178,16 +181,16 @@ class Server:
             req, reserved = self._admit()
             if req is None:
                 return
+            slot = {"reserved": reserved}
             try:
-                res = self._serve_one(req, reserved, stream)
+                res = self._serve_one(req, slot, stream)
                 with self._cv:
                     self._results.append(res)
-                reserved = res.reserved_bytes
             except BaseException as e:  # surface in run()
                 with self._cv:
                     self._errors.append(e)
             finally:
-                self._adjust(reserved, 0)
+                self._adjust(slot["reserved"], 0)
 
     # -- driver ------------------------------------------------------------------
     def run(self, requests, realtime: bool = True) -> List[SolveResult]:

@@ -177,3 +177,20 @@ def test_server_request_matches_oracle(sgp, orc):
     a = np.zeros((1800, 1), dtype=np.float32)
     a[:n, 0] = res.alpha
     _assert_mean(olat, a, res.mean, n)
+
+
+def test_server_failing_request_releases_its_reservation(sgp):
+    """A request that fails after its lattice is built (noise < 0 is rejected
+    by cg_solve) surfaces its error from run(), the other requests are
+    served, and every reserved byte is released."""
+    from paper_2106_06695_amd import serve
+    reqs = _requests(count=6, seed=1107)
+    reqs[2].noise = -1.0
+    srv = serve.Server(workers=3)
+    _note("server with one failing request")
+    with pytest.raises(sgp.SGPError) as ei:
+        srv.run(reqs, realtime=False)
+    assert ei.value.code == -1
+    assert srv._reserved == 0
+    assert 0 < srv.max_reserved <= srv.budget
+    assert sorted(r.rid for r in srv._results) == [q.rid for q in reqs if q.rid != 2]
