@@ -54,6 +54,27 @@ def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, c
     return 0.0
 
 
+def survey_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool) -> float:
+    """Algorithmic HBM bytes of ONE launch under the survey's byte model:
+    fp32 values, int32 indices and fp32 weights whatever precision a kernel
+    computes in, neighbour lists counted once per sweep. The splat stage is
+    k_splat_tile + k_splat_gather + k_gather_fix; inside CG the slice also
+    reads the direction p once and every vector pass counts n*C*4 bytes."""
+    D = d + 1
+    chains = 2 if sym else 1
+    if kind == "splat_stage":
+        return n * D * 8 + n * C * 4 + m * C * 4
+    if kind == "blur":
+        return blur_bytes_per_mvm(d, m, C, r, sym, False) / blur_launches(d, r)
+    if kind == "slice":      # CG variant: idx + w, U, out, and p
+        return n * D * 8 + chains * m * C * 4 + 2 * n * C * 4
+    if kind == "cg_update":  # q, r in; r out
+        return 3 * n * C * 4
+    if kind == "cg_dir":     # p, r, x in; p, x out
+        return 5 * n * C * 4
+    return 0.0
+
+
 def blur_launches(d, r):
     """Launches per blur: with a three-tap stencil two direction steps share
     a launch (the intermediate lattice values stay in registers)."""
@@ -88,18 +109,26 @@ def sources_digest() -> dict:
     return {f: hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() for f in TRAFFIC_SOURCES}
 
 
+TRAFFIC_KERNELS = {"splat": ["k_splat_tile"], "splat_stage": ["k_splat_tile", "k_splat_gather", "k_gather_fix"],
+                   "blur": ["k_blur"], "slice": ["k_slice_tile"], "cg_update": ["k_cg_update"],
+                   "cg_dir": ["k_cg_dir"]}
+
+
 def stored_traffic(stage: str):
-    """HBM bytes per launch of a stage from the committed FETCH_SIZE /
-    WRITE_SIZE measurement (copy-calibrated), or None if the kernel sources
-    changed since."""
+    """HBM bytes per launch of a kernel (or the splat stage) from the
+    committed FETCH_SIZE / WRITE_SIZE measurement (copy-calibrated), or None
+    if the kernel sources changed since."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if t.get("source_sha256") != sources_digest():
         return None
-    k = t.get("stages", {}).get(stage)
-    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+    ks = t.get("kernels", {})
+    names = TRAFFIC_KERNELS.get(stage, [])
+    if not names or any(k not in ks for k in names):
+        return None
+    return sum(ks[k]["fetch_bytes"] + ks[k]["write_bytes"] for k in names)
 
 
 def probe():
@@ -128,17 +157,26 @@ def probe():
 
 def cpu_baseline(w, n_sample: int, iters: int):
     """The oracle as it stands: build + per-column CG on the first n_sample
-    points, single-threaded."""
+    points, single-threaded and pinned to one core of the host."""
     import oracle
+    model, _ = _host_cpu()
+    before = os.sched_getaffinity(0)
+    core = min(before)
     Xs, Vs = w.X[:n_sample], w.values[:n_sample].astype(np.float64)
-    t0 = time.perf_counter()
-    olat = oracle.Lattice(Xs, w.lengthscales)
-    olat.cg(Vs, w.noise, 0.0, max_iter=iters)
-    dt = time.perf_counter() - t0
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        olat = oracle.Lattice(Xs, w.lengthscales)
+        olat.cg(Vs, w.noise, 0.0, max_iter=iters)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, before)
     C = w.values.shape[1]
     return {"value": n_sample * C * iters / dt, "unit": "points*ch/s", "cores": 1, "kind": "oracle",
+            "pinned_core": core, "host": model,
             "sample": f"first {n_sample} of {w.n} points, all {C} columns: oracle build + {iters} "
-                      f"CG iterations per column (fp64, single thread), {dt:.2f} s"}
+                      f"CG iterations per column (fp64, single thread pinned to core {core}), "
+                      f"{dt:.2f} s"}
 
 
 def _host_cpu():
@@ -193,6 +231,104 @@ def cpu_baseline_all_cores(w, n_sample: int, iters: int):
             "host": f"{model}, {ncpu} cores available",
             "sample": f"first {n_sample} of {w.n} points, {C} columns: per column an oracle build + "
                       f"{iters} CG iterations (fp64), {dt:.2f} s wall"}
+
+
+def _median_ms(fn, reps: int):
+    import torch
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts))
+
+
+def configs_bench(sgp):
+    """The other workloads of the benchmark set, each timed on its own
+    (median of warm repetitions, host clock around synchronised calls):
+      ws1  n=2,000 d=3 C=1: latency of build, one MVM and CG to 1e-4;
+      ws2  n=500,000 d=8 C=1: 100 repeated fp32 MVMs and CG to 1e-2;
+      ws4  n=1,000,000 d=16 C=8: forward fp32 MVM and the adjoint with
+           respect to X and the log-lengthscales (Section 4.2)."""
+    import torch
+    import workloads
+    out = {}
+
+    # ws1: small-problem latency
+    w = workloads.ws1()
+    X = torch.from_numpy(w.X).cuda()
+    V = torch.from_numpy(w.values).cuda()
+    lat = sgp.lattice_build(X, w.lengthscales)
+    y = torch.empty_like(V)
+    sgp.lattice_mvm(lat, V, y)
+    x, its, rel = sgp.cg_solve(lat, V, w.noise, w.tol, max_iter=w.max_iter)
+    build_ms = _median_ms(lambda: sgp.lattice_build(X, w.lengthscales).free(), 20)
+    mvm_ms = _median_ms(lambda: sgp.lattice_mvm(lat, V, y), 50)
+    cg_ms = _median_ms(lambda: sgp.cg_solve(lat, V, w.noise, w.tol, max_iter=w.max_iter, x=x), 20)
+
+    def whole():
+        L = sgp.lattice_build(X, w.lengthscales)
+        sgp.lattice_mvm(L, V, y)
+        sgp.cg_solve(L, V, w.noise, w.tol, max_iter=w.max_iter, x=x)
+        L.free()
+    out["ws1"] = {"workload": "n=2,000 d=3 X~N(0,I) l=1 C=1, CG on K+0.1I to 1e-4", "m": lat.m,
+                  "build_ms": build_ms, "mvm_ms": mvm_ms, "cg_ms": cg_ms, "cg_iterations": int(its[0]),
+                  "cg_rel_residual": float(rel[0]), "build_mvm_cg_ms": _median_ms(whole, 20)}
+    lat.free()
+
+    # ws2: single-column throughput
+    w = workloads.ws2()
+    X = torch.from_numpy(w.X).cuda()
+    V = torch.from_numpy(w.values).cuda()
+    build_ms = _median_ms(lambda: sgp.lattice_build(X, w.lengthscales).free(), 5)
+    lat = sgp.lattice_build(X, w.lengthscales)
+    y = torch.empty_like(V)
+    sgp.lattice_mvm(lat, V, y)
+    reps = 100
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sgp.lattice_mvm(lat, V, y)
+    torch.cuda.synchronize()
+    mvm_s = (time.perf_counter() - t0) / reps
+    B = mvm_bytes(w.n, w.d, lat.m, 1, 1, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, its, rel = sgp.cg_solve(lat, V, w.noise, w.tol, max_iter=w.max_iter)
+    cg_s = time.perf_counter() - t0
+    out["ws2"] = {"workload": "n=500,000 d=8 20-component mixture, l~logU[0.5,2], C=1; "
+                              "100 repeated MVMs; CG on K+0.05I to 1e-2",
+                  "m": lat.m, "build_ms": build_ms, "mvm_ms": mvm_s * 1e3,
+                  "mvm_points_ch_per_s": w.n / mvm_s, "mvm_algo_bytes": B,
+                  "mvm_algo_GBps": B / mvm_s / 1e9, "mvm_frac_of_hbm_peak": B / mvm_s / 1e9 / HBM_PEAK_GBS,
+                  "cg_ms": cg_s * 1e3, "cg_iterations": int(its[0]), "cg_rel_residual": float(rel[0]),
+                  "cg_ms_per_iteration": cg_s * 1e3 / max(1, int(its[0]))}
+    lat.free()
+
+    # ws4: forward MVM and adjoint
+    w = workloads.ws4()
+    X = torch.from_numpy(w.X).cuda()
+    V = torch.from_numpy(w.values).cuda()
+    G = torch.from_numpy(np.random.default_rng(4).standard_normal(w.values.shape).astype(np.float32)).cuda()
+    build_ms = _median_ms(lambda: sgp.lattice_build(X, w.lengthscales).free(), 3)
+    lat = sgp.lattice_build(X, w.lengthscales)
+    y = torch.empty_like(V)
+    sgp.lattice_mvm(lat, V, y)
+    mvm_ms = _median_ms(lambda: sgp.lattice_mvm(lat, V, y), 10)
+    sgp.lattice_mvm_grad(lat, X, V, G)
+    adj_ms = _median_ms(lambda: sgp.lattice_mvm_grad(lat, X, V, G), 3)
+    B = mvm_bytes(w.n, w.d, lat.m, w.C, 1, True)
+    out["ws4"] = {"workload": "n=1,000,000 d=16 X~U[-1,1]^16, l~logU[0.3,3], C=8; forward MVM "
+                              "and adjoint (dX, dlog l) of sum(G * K V)",
+                  "m": lat.m, "build_ms": build_ms, "mvm_ms": mvm_ms,
+                  "mvm_points_ch_per_s": w.n * w.C / (mvm_ms / 1e3), "mvm_algo_bytes": B,
+                  "mvm_algo_GBps": B / (mvm_ms / 1e3) / 1e9,
+                  "mvm_frac_of_hbm_peak": B / (mvm_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                  "adjoint_ms": adj_ms, "adjoint_points_ch_per_s": w.n * w.C / (adj_ms / 1e3)}
+    lat.free()
+    return out
 
 
 def serving_bench(workers: int, count: int, rhos=(0.5, 0.9, 1.5), seed: int = 1005):
@@ -283,8 +419,10 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="points in the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--mvm-reps", type=int, default=20, help="extra timed lattice_mvm calls")
-    ap.add_argument("--serve", type=int, default=0,
-                    help="also run the serving benchmark with this many requests (0 = skip)")
+    ap.add_argument("--serve", type=int, default=256,
+                    help="requests of the serving benchmark (0 = skip)")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="1: also time the n=2,000, n=500,000 and n=1,000,000 (d=16) workloads")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: autotune the MVM launch shapes on the first lattice before timing")
@@ -350,16 +488,36 @@ def main(argv=None):
             avg = ms / launches
             kernels[kind] = {"launches": launches, "total_ms": round(ms, 3), "avg_us": round(avg * 1e3, 2),
                              "algo_GBps": round(b / (avg / 1e3) / 1e9, 1) if b else None}
-    # the splat runs as two passes (per-tile reduction, then per-lattice-point
-    # gather of the tile partials, whose small fix-up kernel for lattice
-    # points spanning several gather ranges is timed with it); its
-    # algorithmic bytes cover all three kernels
-    stage_ms = {k: kernels[k]["total_ms"] for k in ("blur", "slice") if k in kernels}
-    stage_ms["splat"] = kernels["splat"]["total_ms"] + kernels.get("splat_gather", {"total_ms": 0.0})["total_ms"]
-    dom = max(stage_ms, key=stage_ms.get)
-    dom_bytes = kernel_bytes(dom, n, d, m, C, 1, sym, cg=True)
-    dom_avg_s = stage_ms[dom] / kernels[dom]["launches"] / 1e3
-    achieved = dom_bytes / dom_avg_s / 1e9
+    # Roofline of the kernel with the largest time per step, and of the
+    # splat stage (k_splat_tile, then k_splat_gather + k_gather_fix, which
+    # the "splat_gather" kind times together). "achieved" uses the survey's
+    # byte model (fp32 values whatever precision the kernel computes in);
+    # "achieved_operand_bytes" the kernel's own operand widths (fp64 values
+    # and lattice rows inside CG).
+    def roof(kind_label, kinds, survey_b, native_b, traffic_key):
+        tot = sum(kernels[k]["total_ms"] for k in kinds if k in kernels)
+        avg_s = tot / kernels[kinds[0]]["launches"] / 1e3
+        a_s = survey_b / avg_s / 1e9
+        a_n = native_b / avg_s / 1e9
+        return {"bound": "hbm", "kernel": kind_label, "avg_us": avg_s * 1e6,
+                "achieved": a_s, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a_s / HBM_PEAK_GBS,
+                "traffic": stored_traffic(traffic_key), "algo_bytes_per_launch": survey_b,
+                "byte_model": "survey (fp32 values, int32 indices, fp32 weights)",
+                "achieved_operand_bytes": a_n, "frac_operand_bytes": a_n / HBM_PEAK_GBS,
+                "operand_bytes_per_launch": native_b}
+
+    names = {"splat": "k_splat_tile", "blur": "k_blur2_split / k_blur2", "slice": "k_slice_tile<double, G, true>",
+             "cg_update": "k_cg_update", "cg_dir": "k_cg_dir"}
+    single = {k: kernels[k]["total_ms"] for k in names if k in kernels}
+    dom = max(single, key=single.get)
+    splat_native = kernel_bytes("splat", n, d, m, C, 1, sym, cg=True)
+    dom_survey = {"splat": n * (d + 1) * 8 + n * C * 4}.get(dom, survey_bytes(dom, n, d, m, C, 1, sym))
+    dom_native = kernel_bytes(dom, n, d, m, C, 1, sym, cg=True)
+    if dom == "splat":  # the tile kernel alone reads W and V; U is written by the gather
+        dom_native -= m * C * 8
+    roofline = roof(names[dom], [dom], dom_survey, dom_native, dom)
+    splat_stage = roof("k_splat_tile + k_splat_gather + k_gather_fix", ["splat", "splat_gather"],
+                       survey_bytes("splat_stage", n, d, m, C, 1, sym), splat_native, "splat_stage")
 
     # standalone MVMs on a resident lattice (outside the timed steps)
     lat = sgp.lattice_build(X, w.lengthscales, blur=args.blur)
@@ -409,13 +567,12 @@ def main(argv=None):
                                "Rademacher probes), noise 0.05, RBF r=1, " + args.blur + " blur, 20 CG iterations",
                    "n": n, "d": d, "C": C, "m": m, "m_over_L": m / (n * (d + 1)),
                    "cg_iterations": iters, "blur": args.blur},
-        "roofline": {"bound": "hbm", "kernel": dom + (" (splat_tile + splat_gather + gather_fix)" if dom == "splat" else ""),
-                     "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom),
-                     "algo_bytes_per_launch": dom_bytes},
+        "roofline": roofline,
+        "splat_stage": splat_stage,
         "mvm_only": {"ms": mvm_s * 1e3, "points_ch_per_s": n * C / mvm_s,
                      "algo_bytes": B, "algo_GBps": B / mvm_s / 1e9,
-                     "frac_of_hbm_peak": B / mvm_s / 1e9 / HBM_PEAK_GBS},
+                     "frac_of_hbm_peak": B / mvm_s / 1e9 / HBM_PEAK_GBS,
+                     "byte_model": "survey B_mvm (fp32 lattice_mvm, C=16)"},
         "batched_vs_separate": {"cg_iterations": iters, "batched_C16_ms": (t1 - t0) * 1e3,
                                 "separate_16x_C1_ms": (t2 - t1) * 1e3,
                                 "speedup": (t2 - t1) / (t1 - t0)},
@@ -425,6 +582,8 @@ def main(argv=None):
     }
     if paper is not None:
         line["paper_sparsity"] = paper
+    if args.configs:
+        line["configs"] = configs_bench(sgp)
     if args.serve > 0:
         line["serving"] = serving_bench(args.serve_workers, args.serve)
     if args.cpu_sample > 0:
