@@ -129,13 +129,15 @@ def test_out_of_memory_flushes_idle_cache_and_retries(sgp):
         sgp.debug_inject_oom(0)
     assert lat2.m > 0
     lat2.free()
-    # both attempts fail: the error is reported, nothing leaks
+    # both attempts fail: the error is reported, nothing leaks (a larger
+    # build than any before, so that its blocks cannot come from the cache)
     lat, _ = _run(sgp, w, G)
     lat.free()
+    big = workloads.small_case(80, 150000, 7, channels=1, kind="mixture")
     sgp.debug_inject_oom(2)
     try:
         with pytest.raises(sgp.SGPError) as ei:
-            sgp.lattice_build(_cuda(other.X), other.lengthscales)
+            sgp.lattice_build(_cuda(big.X), big.lengthscales)
         assert ei.value.code == -2
     finally:
         sgp.debug_inject_oom(0)
