@@ -72,7 +72,9 @@ typedef struct sgp_opts {
   int32_t kernel;    /* enum sgp_kernel (default SGP_KERNEL_RBF) */
   int32_t blur;      /* enum sgp_blur (default SGP_BLUR_SYMMETRIC) */
   float outputscale; /* sigma_f^2 multiplying the whole operator (default 1) */
-  float load_factor; /* hash table fill bound relative to n(d+1), in (0, 0.9] (default 0.5) */
+  float load_factor; /* hash table fill bound relative to n(d+1), in (0, 0.9]; 0 (default) =
+                        automatic: the shape sgp_autotune_build chose for builds of this
+                        d and size class, else 0.5 */
   int64_t solve_rows; /* cg_solve uses only the first solve_rows points (0 = all, default):
                          the others splat zero and get x = 0, so a lattice built on
                          [X; X_test] solves with X's block of the joint operator and one
@@ -217,6 +219,14 @@ int sgp_cg_graph_enable(int on);
  * setting. */
 int sgp_blur_fuse_enable(int on);
 
+/* CG direction update fused into the splat (process-wide switch, default
+ * on). Each iteration's x += alpha p and p = r + beta p (Section 2, the
+ * conjugate-gradient recurrence) then run in the next iteration's splat,
+ * which reads every element of p anyway, and the last one in the final copy
+ * of x; off, they run as a pass of their own. The arithmetic is the same, so
+ * results are bitwise identical either way. Returns the previous setting. */
+int sgp_cg_fuse_enable(int on);
+
 /* Autotuning of the MVM's launch shape (the multi-column lattice filter of
  * Section 3.2, batched as in the mBCG solver of Section 2). Times every
  * candidate on lattice L for C columns, fp64 (the CG path, C <= 64) or
@@ -235,8 +245,26 @@ int sgp_blur_fuse_enable(int on);
 int sgp_autotune(const sgp_lattice* L, int32_t C, int32_t fp64, int32_t reps, void* stream,
                  int32_t* choice, float* ms_per_mvm);
 
-/* Forget every autotuned choice (later calls use the default shapes). */
+/* Forget every autotuned choice, the MVM's and the build's (later calls use
+ * the default shapes). */
 int sgp_autotune_reset(void);
+
+/* Autotuning of the lattice build's hash table (the table into which every
+ * simplex vertex is inserted, Section 3.2, Splat): times lattice_build of X
+ * (reps timed builds after one warm-up, each synchronised and freed) for
+ * each candidate table shape, i.e. a load factor (full table of
+ * n(d+1)/load_factor slots) and the first attempt's reduction of it by
+ * 2^shrink (a build whose reduced table fills up repeats with the full one),
+ * and keeps the fastest process-wide for builds of the same d and size class
+ * (n(d+1) rounded up to a power of two) whose opts->load_factor is 0. No
+ * choice changes any result: lattice points are numbered by first
+ * occurrence, not by table slot. opts as for lattice_build (its load_factor
+ * is ignored). Outputs (host, may be NULL): the chosen load factor and
+ * shrink, and the time of one build with them. Errors as lattice_build,
+ * and SGP_EINVAL for reps < 1. Synchronises `stream`. */
+int sgp_autotune_build(const float* X, int64_t n, int32_t d, const double* lengthscales,
+                       const sgp_opts* opts, int32_t reps, void* stream, float* load_factor,
+                       int32_t* shrink, float* ms_per_build);
 
 /* Kernel timing with HIP events, for benchmarks. While enabled, every
  * kernel launch of the library is bracketed by two events on its stream.

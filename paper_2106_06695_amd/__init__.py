@@ -111,7 +111,7 @@ class Lattice:
 
 def lattice_build(X, lengthscales: Sequence[float], order: int = 1, kernel: str = "rbf",
                   blur: str = "symmetric", outputscale: float = 1.0,
-                  load_factor: float = 0.5, solve_rows: int = 0) -> Lattice:
+                  load_factor: float = 0.0, solve_rows: int = 0) -> Lattice:
     """Build the lattice of X (n x d fp32 CUDA tensor); see lattice_build in
     include/simplexgp.h (Section 3.2 of the paper: Splat and Blur)."""
     lib = _lib.load()
@@ -278,6 +278,12 @@ def cg_graph_enable(on: bool) -> bool:
     return bool(_lib.load().sgp_cg_graph_enable(1 if on else 0))
 
 
+def cg_fuse_enable(on: bool) -> bool:
+    """Switch the CG direction update between the splat (on, default) and a
+    pass of its own; returns the previous setting. Results are identical."""
+    return bool(_lib.load().sgp_cg_fuse_enable(1 if on else 0))
+
+
 def blur_fuse_enable(on: bool) -> bool:
     """Turn fused two-step blur launches on or off (process-wide); returns
     the previous setting. Results do not depend on it."""
@@ -297,8 +303,32 @@ def autotune(lat: Lattice, C: int, fp64: bool = True, reps: int = 3) -> dict:
             "ms_per_mvm": ms.value}
 
 
+def autotune_build(X, lengthscales: Sequence[float], reps: int = 2, order: int = 1,
+                   kernel: str = "rbf", blur: str = "symmetric") -> dict:
+    """Time lattice builds of X for each hash-table shape (load factor and
+    first-attempt reduction) and keep the fastest for builds of the same d
+    and size class whose load_factor is 0 (the default); see
+    sgp_autotune_build in include/simplexgp.h. Results do not depend on it."""
+    lib = _lib.load()
+    n, d = int(X.shape[0]), int(X.shape[1])
+    px = _dev_f32(X, "X")
+    ell = np.ascontiguousarray(np.asarray(lengthscales, dtype=np.float64).reshape(-1))
+    if ell.shape[0] != d:
+        raise ValueError("lengthscales must have d entries")
+    opts = _lib.Opts()
+    lib.sgp_opts_default(ctypes.byref(opts))
+    opts.order = int(order)
+    opts.kernel = _KERNEL[kernel]
+    opts.blur = _BLUR[blur]
+    lf, sh, ms = ctypes.c_float(), ctypes.c_int32(), ctypes.c_float()
+    _check(lib.sgp_autotune_build(px, n, d, ell.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
+                                  int(reps), _stream(X.device), ctypes.byref(lf), ctypes.byref(sh),
+                                  ctypes.byref(ms)))
+    return {"load_factor": lf.value, "shrink": int(sh.value), "ms_per_build": ms.value}
+
+
 def autotune_reset() -> None:
-    """Forget every autotuned launch choice."""
+    """Forget every autotuned choice (MVM launch shapes and build shapes)."""
     _check(_lib.load().sgp_autotune_reset())
 
 

@@ -35,9 +35,11 @@ SIGNATURES = {
     "sgp_debug_inject_oom": (ctypes.c_int, [_I32]),
     "sgp_cg_graph_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_blur_fuse_enable": (ctypes.c_int, [ctypes.c_int]),
+    "sgp_cg_fuse_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sgp_autotune_reset": (ctypes.c_int, []),
+    "sgp_autotune_build": (ctypes.c_int, [_P, _I64, _I32, _P, _P, _I32, _P, _P, _P, _P]),
     "sgp_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_profile_reset": (ctypes.c_int, []),
     "sgp_profile_kinds": (ctypes.c_int, []),

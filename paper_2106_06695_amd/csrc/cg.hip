@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
   });
 }
 
-// r -= alpha q, and r.r (x moves in k_cg_dir, which reads p anyway).
+// r -= alpha q, and r.r (x and p move in the next splat, which reads p
+// anyway, or in k_cg_dir).
 __global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ r,
                                                       const double* __restrict__ q_, int64_t n, int C,
                                                       const CgState* __restrict__ st,
@@ -193,10 +194,26 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(float* __restrict__ x, const 
   }
 }
 
-// x back to the caller's order: one thread per (row, four channels).
+}  // namespace
+
+int launch_cg_dir(const CgDirUpdate& up, int64_t nC, int C, hipStream_t s) {
+  ProfScope ps(KK_CG_DIR, s);
+  const dim3 grid((unsigned)std::min<int64_t>((nC / 2 + kBlock - 1) / kBlock + 1, 65536));
+  hipLaunchKernelGGL(k_cg_dir, grid, dim3(kBlock), 0, s, up.x, up.r, up.p, nC, C, up.st);
+  SGP_LAUNCH_CHECK("k_cg_dir");
+  return SGP_OK;
+}
+
+namespace {
+
+// x back to the caller's order: one thread per (row, four channels). When
+// the direction update runs in the splat (p non-null), the last iteration's
+// x += alpha p is still due and is applied here, as the update would.
 __global__ __launch_bounds__(kBlock) void k_cg_out(const float* __restrict__ xs,
                                                    const uint32_t* __restrict__ perm,
-                                                   float* __restrict__ x, int64_t n, int C, int vec) {
+                                                   float* __restrict__ x, int64_t n, int C, int vec,
+                                                   const double* __restrict__ p,
+                                                   const CgState* __restrict__ st) {
   const int ng = (C + 3) / 4;
   const int64_t total = n * ng;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -205,10 +222,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_out(const float* __restrict__ xs,
     const int c = (int)(t - i * ng) * 4;
     const float* src = xs + i * C + c;
     float* dst = x + (int64_t)perm[i] * C + c;
+    float v[4];
     if (vec) {
-      *(float4*)dst = *(const float4*)src;
+      const float4 a = *(const float4*)src;
+      v[0] = a.x;
+      v[1] = a.y;
+      v[2] = a.z;
+      v[3] = a.w;
     } else {
-      for (int k = 0; k < 4 && c + k < C; ++k) dst[k] = src[k];
+      for (int k = 0; k < 4; ++k) v[k] = c + k < C ? src[k] : 0.f;
+    }
+    if (p) {
+      for (int k = 0; k < 4 && c + k < C; ++k)
+        v[k] = (float)__builtin_fma(st->alpha[c + k], p[i * C + c + k], (double)v[k]);
+    }
+    if (vec) {
+      *(float4*)dst = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      for (int k = 0; k < 4 && c + k < C; ++k) dst[k] = v[k];
     }
   }
 }
@@ -248,7 +279,6 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   const dim3 igrid((unsigned)std::min<int64_t>(iparts, 65536));
   const dim3 ugrid((unsigned)std::min<int64_t>(uparts, 65536));
   const size_t vlds = cg_vec_lds(C);
-  const dim3 dgrid((unsigned)std::min<int64_t>((nC / 2 + kBlock - 1) / kBlock + 1, 65536));
   const CgHook h_start{partials, iparts, st, counter, (int)SM_START, (double)tol};
   const CgHook h_alpha{partials, L->ntiles, st, counter, (int)SM_ALPHA, (double)tol};
   const CgHook h_beta{partials, uparts, st, counter, (int)SM_BETA, (double)tol};
@@ -267,8 +297,13 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   // One iteration: q = A p (the slice's last block turns p.q into alpha),
   // r and its norm, convergence and beta, then x and p. Nothing here talks to the host, so a block of iterations
   // can be recorded as a graph.
-  auto iterate = [&](hipStream_t st_) -> int {
-    int rc_ = mvm_cg(L, p, C, q, st_, (double)noise, &h_alpha);
+  // The direction update x += alpha p, p = r + beta p of an iteration runs
+  // in the next iteration's splat (CgDirUpdate), or as a pass of its own
+  // when that fusion is switched off; both give the same values bit for bit.
+  const bool fused = cg_fuse_enabled();
+  const CgDirUpdate dirup{p, r, x32, st};
+  auto iterate = [&](hipStream_t st_, bool first) -> int {
+    int rc_ = mvm_cg(L, p, C, q, st_, (double)noise, &h_alpha, (fused && !first) ? &dirup : nullptr);
     if (rc_) return rc_;
     {
       ProfScope ps(KK_CG_UPDATE, st_);
@@ -280,10 +315,9 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
       hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, h_beta, C);
       SGP_LAUNCH_CHECK("k_cg_scalar");
     }
-    {
-      ProfScope ps(KK_CG_DIR, st_);
-      hipLaunchKernelGGL(k_cg_dir, dgrid, block, 0, st_, x32, r, p, nC, C, (const CgState*)st);
-      SGP_LAUNCH_CHECK("k_cg_dir");
+    if (!fused) {
+      const int rc2 = launch_cg_dir(dirup, nC, C, st_);
+      if (rc2) return rc2;
     }
     return SGP_OK;
   };
@@ -299,14 +333,17 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   };
   const bool polling = tol > 0.f;
   const int blk = polling ? 4 : 8;
-  // The first block and one more iteration run launch by launch: the first
-  // MVM sizes the lattice's work buffers (a graph must not allocate), and a
-  // solve that converges within them never pays for recording a graph.
+  // The first iterations run launch by launch: the first MVM sizes the
+  // lattice's work buffers (a graph must not allocate). With a tolerance,
+  // the first block and one more iteration do, so that a solve converging
+  // within them never pays for recording a graph. With a fixed count, the
+  // head is what leaves the rest a whole number of blocks (at least one
+  // iteration), e.g. 4 + 2 x 8 for 20 iterations.
   int it = 0;
   bool done = false;
-  const int eager_head = blk + 1 < max_iter ? blk + 1 : max_iter;
+  const int eager_head = polling ? (blk + 1 < max_iter ? blk + 1 : max_iter) : (max_iter - 1) % blk + 1;
   for (; it < eager_head && !done; ++it) {
-    if ((rc = iterate(s))) return rc;
+    if ((rc = iterate(s, it == 0))) return rc;
     if (polling && (it + 1) % blk == 0 && it + 1 < max_iter)
       if ((rc = all_done(&done))) return rc;
   }
@@ -334,7 +371,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     } guard{&graph, &exec, s};
     SGP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int crc = SGP_OK;
-    for (int b = 0; b < blk && !crc; ++b) crc = iterate(cs);
+    for (int b = 0; b < blk && !crc; ++b) crc = iterate(cs, false);
     hipError_t ce = hipStreamEndCapture(cs, &graph);
     if (crc) return crc;
     SGP_HIP(ce);
@@ -347,7 +384,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     }
   }
   for (; it < max_iter && !done; ++it) {
-    if ((rc = iterate(s))) return rc;
+    if ((rc = iterate(s, it == 0))) return rc;
     if (polling && (it + 1) % blk == 0 && it + 1 < max_iter)
       if ((rc = all_done(&done))) return rc;
   }
@@ -356,7 +393,8 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     const int vec = (C % 4 == 0 && ((uintptr_t)x & 15u) == 0) ? 1 : 0;
     const int64_t work = n * ((C + 3) / 4);
     hipLaunchKernelGGL(k_cg_out, dim3((unsigned)std::min<int64_t>((work + kBlock - 1) / kBlock, 65536)), block, 0, s,
-                       (const float*)x32, (const uint32_t*)L->perm.ptr, x, n, C, vec);
+                       (const float*)x32, (const uint32_t*)L->perm.ptr, x, n, C, vec,
+                       fused ? (const double*)p : (const double*)nullptr, (const CgState*)st);
     SGP_LAUNCH_CHECK("k_cg_out");
   }
   SGP_HIP(hipMemcpyAsync(host, st->iters, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));

@@ -21,6 +21,17 @@ struct CgState {
 
 enum ScalarMode { SM_START = 0, SM_ALPHA = 1, SM_BETA = 2 };
 
+// The previous iteration's direction update, applied by the next MVM's
+// splat as it stages the direction (the splat reads p anyway): x += alpha p
+// with that iteration's alpha, then p = r + beta p for the columns still
+// active, p updated in place. p == nullptr: no update (the first iteration).
+struct CgDirUpdate {
+  double* p;
+  const double* r;
+  float* x;
+  const CgState* st;
+};
+
 // What a partial-sum kernel needs to finish the step itself.
 struct CgHook {
   double* partials;   // nparts x C

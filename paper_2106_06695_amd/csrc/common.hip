@@ -466,6 +466,7 @@ namespace sgp {
 namespace {
 std::atomic<int> g_cg_graph{1};
 std::atomic<int> g_blur_fuse{1};
+std::atomic<int> g_cg_fuse{1};
 }
 bool profiling() {
   std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -473,6 +474,7 @@ bool profiling() {
 }
 bool cg_graphs_enabled() { return g_cg_graph.load() != 0; }
 bool blur_fuse_enabled() { return g_blur_fuse.load() != 0; }
+bool cg_fuse_enabled() { return g_cg_fuse.load() != 0; }
 hipStream_t capture_stream() {
   constexpr int kMaxDevices = 64;
   thread_local hipStream_t streams[kMaxDevices] = {};
@@ -492,7 +494,7 @@ void sgp_opts_default(sgp_opts* o) {
   o->kernel = SGP_KERNEL_RBF;
   o->blur = SGP_BLUR_SYMMETRIC;
   o->outputscale = 1.0f;
-  o->load_factor = 0.5f;
+  o->load_factor = 0.0f;  // automatic: the autotuned table shape, else 0.5
   o->solve_rows = 0;
 }
 
@@ -612,6 +614,7 @@ int sgp_debug_inject_oom(int32_t count) {
 }
 
 int sgp_cg_graph_enable(int on) { return g_cg_graph.exchange(on != 0 ? 1 : 0); }
+int sgp_cg_fuse_enable(int on) { return g_cg_fuse.exchange(on != 0 ? 1 : 0); }
 int sgp_blur_fuse_enable(int on) { return g_blur_fuse.exchange(on != 0 ? 1 : 0); }
 
 int sgp_profile_enable(int on) {

@@ -26,8 +26,10 @@
 // host rebuilds with a new seed if any differ, so the final lattice is
 // exact.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "sgp_internal.h"
@@ -1393,6 +1395,49 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
 
 using namespace sgp;
 
+// Hash-table shape of a build: the load factor bounding the full table
+// (L / load_factor slots for L = n(d+1) splat entries) and the first
+// attempt's reduction of it (2^shrink times smaller; a build whose table
+// fills up repeats with the full one). Neither changes any result: lattice
+// points are numbered by first occurrence, not by slot.
+namespace sgp {
+namespace {
+struct BuildShape {
+  float load_factor;
+  int shrink;
+};
+struct BuildTuneEntry {
+  int d, llog;
+  BuildShape shape;
+  float ms;
+};
+std::mutex g_build_tune_mu;
+std::vector<BuildTuneEntry> g_build_tune;          // process-wide, keyed by (d, size class)
+thread_local const BuildShape* g_build_force = nullptr;  // set while candidates are timed
+constexpr BuildShape kDefaultShape{0.5f, 3};
+
+int llog_of(int64_t L) {
+  int b = 0;
+  while (((int64_t)1 << b) < L) ++b;
+  return b;
+}
+
+BuildShape build_shape(int64_t n, int d, float load_factor) {
+  if (g_build_force) return *g_build_force;
+  if (load_factor > 0.f) return BuildShape{load_factor, kDefaultShape.shrink};
+  std::lock_guard<std::mutex> lk(g_build_tune_mu);
+  for (const BuildTuneEntry& e : g_build_tune)
+    if (e.d == d && e.llog == llog_of(n * (d + 1))) return e.shape;
+  return kDefaultShape;
+}
+}  // namespace
+
+void build_tune_reset() {
+  std::lock_guard<std::mutex> lk(g_build_tune_mu);
+  g_build_tune.clear();
+}
+}  // namespace sgp
+
 extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double* lengthscales,
                              const sgp_opts* opts, void* stream, sgp_lattice** out) {
   if (!out) {
@@ -1442,10 +1487,11 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
     set_error("lattice_build: solve_rows must be in [0, n]");
     return SGP_EINVAL;
   }
-  if (!(o.load_factor > 0.0f && o.load_factor <= 0.9f)) {
-    set_error("lattice_build: load_factor must be in (0, 0.9]");
+  if (!(o.load_factor == 0.0f || (o.load_factor > 0.0f && o.load_factor <= 0.9f))) {
+    set_error("lattice_build: load_factor must be 0 (automatic) or in (0, 0.9]");
     return SGP_EINVAL;
   }
+  const BuildShape shape = build_shape(n, d, o.load_factor);
 
   hipStream_t st = (hipStream_t)stream;
   sgp_lattice* L = new sgp_lattice();
@@ -1472,11 +1518,11 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
     }
   }
   bool retry = true;
-  int shrink = 3;  // first try a table 8x smaller than the bound
+  int shrink = shape.shrink;  // first try a table 2^shrink times smaller than the bound
   for (int attempt = 0; rc == SGP_OK && retry && attempt < 4;) {
     const unsigned long long seed = 0x5157a11ce5eedull + 0x9e3779b97f4a7c15ull * (unsigned long long)attempt;
     bool grow = false;
-    rc = build_attempt(L, X, f, (double)o.load_factor, seed, shrink, st, host_word, &retry, &grow);
+    rc = build_attempt(L, X, f, (double)shape.load_factor, seed, shrink, st, host_word, &retry, &grow);
     if (rc == SGP_OK && grow) {
       shrink = 0;
       retry = true;
@@ -1500,5 +1546,62 @@ extern "C" int lattice_build(const float* X, int64_t n, int32_t d, const double*
     return rc;
   }
   *out = L;
+  return SGP_OK;
+}
+
+// Times lattice_build of X for every candidate hash-table shape and keeps
+// the fastest for builds of the same d and size class.
+extern "C" int sgp_autotune_build(const float* X, int64_t n, int32_t d, const double* lengthscales,
+                                  const sgp_opts* opts, int32_t reps, void* stream, float* load_factor,
+                                  int32_t* shrink, float* ms_per_build) {
+  using namespace sgp;
+  if (reps < 1) {
+    set_error("sgp_autotune_build: reps must be >= 1");
+    return SGP_EINVAL;
+  }
+  sgp_opts o;
+  sgp_opts_default(&o);
+  if (opts) o = *opts;
+  o.load_factor = 0.f;
+  static const BuildShape kCandidates[] = {{0.25f, 3}, {0.5f, 3}, {0.9f, 3}, {0.5f, 2}, {0.5f, 4},
+                                           {0.5f, 0}, {0.9f, 0}};
+  BuildShape best = kDefaultShape;
+  float best_ms = -1.f;
+  struct Reset {
+    ~Reset() { g_build_force = nullptr; }
+  } reset;
+  for (const BuildShape& cand : kCandidates) {
+    g_build_force = &cand;
+    float ms = 0.f;
+    for (int r = 0; r <= reps; ++r) {  // one warm-up, then reps timed builds
+      sgp_lattice* L = nullptr;
+      const auto t0 = std::chrono::steady_clock::now();
+      const int rc = lattice_build(X, n, d, lengthscales, &o, stream, &L);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (rc) return rc;
+      lattice_free(L);
+      if (r > 0) ms += std::chrono::duration<float, std::milli>(t1 - t0).count();
+    }
+    ms /= (float)reps;
+    if (best_ms < 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = cand;
+    }
+  }
+  g_build_force = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_build_tune_mu);
+    const BuildTuneEntry e{(int)d, llog_of(n * (d + 1)), best, best_ms};
+    bool found = false;
+    for (BuildTuneEntry& x : g_build_tune)
+      if (x.d == e.d && x.llog == e.llog) {
+        x = e;
+        found = true;
+      }
+    if (!found) g_build_tune.push_back(e);
+  }
+  if (load_factor) *load_factor = best.load_factor;
+  if (shrink) *shrink = best.shrink;
+  if (ms_per_build) *ms_per_build = best_ms;
   return SGP_OK;
 }

@@ -187,14 +187,27 @@ struct SplatArgs {
 // order; a lane group that finishes a run claims the next unclaimed one, so
 // runs of different lengths balance over the groups. The sum lands in the
 // lattice point's block of partial rows (run_dst).
-template <typename TU, int G>
+//
+// Inside CG (up.p set, fp64) the values are the direction p in internal
+// order, and the block applies the previous iteration's direction update to
+// each tile as it stages it (CgDirUpdate): every (point, column) of p is
+// read once here anyway, so x and p move without a pass of their own. Each
+// element is read and written by the one thread that stages it; the new p
+// is what the tile splats.
+// DIR: the fused variant; it is launched only where the tile's values are
+// whole 16-byte vectors of C == G columns in internal order (vec_v).
+template <typename TU, int G, bool DIR>
 __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_splat_tile(
     const int32_t* __restrict__ tile_off, const uint16_t* __restrict__ run_rel,
     const int32_t* __restrict__ run_dst, const uint8_t* __restrict__ ent_lp,
     const float* __restrict__ ent_w, const TU* __restrict__ V, const uint32_t* __restrict__ perm,
-    TU* __restrict__ part, SplatArgs<TU> a) {
+    TU* __restrict__ part, SplatArgs<TU> a, CgDirUpdate up) {
   using S = TileShape<TU, G, kSplatBlock>;
   extern __shared__ __align__(16) unsigned char smem[];
+  // CG: alpha, beta and the active flags of the columns, for the update
+  __shared__ double s_alpha[DIR ? kMaxCgCols : 1], s_beta[DIR ? kMaxCgCols : 1];
+  __shared__ int s_active[DIR ? kMaxCgCols : 1];
+  constexpr bool upd = DIR && sizeof(TU) == 8 && S::VEC;
   TU* lv = (TU*)smem;
   float* lw = (float*)(smem + a.lds.w);
   int32_t* ldst = (int32_t*)(smem + a.lds.dst);
@@ -220,7 +233,7 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
     ne = np * a.D;
     q0 = tile_off[t];
     nq = tile_off[t + 1] - q0;
-    if (S::VEC && a.vec_v) {
+    if (S::VEC && (DIR || a.vec_v)) {
       const typename Vec16<TU>::T* src = (const typename Vec16<TU>::T*)(V + p0 * a.C);
       const int nvec = np * G / N;
 #pragma unroll
@@ -267,19 +280,47 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
   int64_t item, end, step;
   xcd_items(a.items, &item, &end, &step);
   for (int i = tid; i < S::RS; i += kSplatBlock) lv[a.P * S::RS + i] = (TU)0;  // the zero row
+  if constexpr (upd) {
+    for (int c = tid; c < a.C && c < kMaxCgCols; c += kSplatBlock) {
+      s_alpha[c] = up.st->alpha[c];
+      s_beta[c] = up.st->beta[c];
+      s_active[c] = up.st->active[c];
+    }
+  }
   if (item < end) fetch(item);
   for (; item < end; item += step) {
     const int cur_nq = nq, cur_ne = ne, cur_q0 = q0;
     __syncthreads();  // the previous tile's runs are done with the LDS
-    if (S::VEC && a.vec_v) {
+    if (S::VEC && (DIR || a.vec_v)) {
+      const int64_t p0 = (item / a.chunks) * a.P;
 #pragma unroll
       for (int u = 0; u < S::VPT / N; ++u) {
         const int vi = tid + u * kSplatBlock;
         if (vi * N < cur_ne / a.D * G) {
           typename Vec16<TU>::T x;
-#pragma unroll
-          for (int j = 0; j < N; ++j) x[j] = v[u * N + j];
           const int f = vi * N;  // N consecutive elements of one row
+          if constexpr (upd) {
+            // C == G here: element f of the tile is column f % G of row f / G
+            typedef float fvN __attribute__((ext_vector_type(N)));
+            const int64_t e = p0 * a.C + f;
+            const typename Vec16<TU>::T r2 = *(const typename Vec16<TU>::T*)((const TU*)up.r + e);
+            const fvN x2 = *(const fvN*)(up.x + e);
+            typename Vec16<TU>::T pn;
+            fvN xn;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+              const int c = (f + j) % G;
+              const TU pold = v[u * N + j];
+              xn[j] = (float)__builtin_fma(s_alpha[c], (double)pold, (double)x2[j]);
+              pn[j] = s_active[c] ? (TU)__builtin_fma(s_beta[c], (double)pold, (double)r2[j]) : pold;
+            }
+            *(typename Vec16<TU>::T*)((TU*)up.p + e) = pn;
+            *(fvN*)(up.x + e) = xn;
+            x = pn;
+          } else {
+#pragma unroll
+            for (int j = 0; j < N; ++j) x[j] = v[u * N + j];
+          }
           *(typename Vec16<TU>::T*)(lv + (f / G) * S::RS + f % G) = x;
         }
       }
@@ -1117,12 +1158,20 @@ void split_rows(int64_t rows, int R, int64_t cap, unsigned* blocks, int64_t* row
   *blocks = (unsigned)((rows + *rows_per_block - 1) / *rows_per_block);
 }
 
+// Work memory of one MVM in elements of its accumulator type: four m x C
+// lattice value arrays (the splat's result and the blur's ping-pong), one
+// partial row per run piece, two fragment rows per gather range.
+size_t mvm_work_elems(const sgp_lattice* L, int C) {
+  return (size_t)(4 * L->m + L->npiece + 2 * gather_ranges(L)) * (size_t)C;
+}
+
 template <typename TU, int G>
 int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out, hipStream_t s,
-          TU noise, const TU* p, const CgHook* hook, const LaunchChoice& lc) {
+          TU noise, const TU* p, const CgHook* hook, const LaunchChoice& lc, void* work,
+          const CgDirUpdate* up) {
   const int d = L->d, D = d + 1, T = 2 * L->order;
   const int64_t m = L->m, mC = m * C;
-  TU* U0 = (TU*)L->ubuf.ptr;
+  TU* U0 = (TU*)work;
   TU* B1 = U0 + mC;
   TU* B2 = B1 + mC;
   TU* B3 = B2 + mC;
@@ -1132,24 +1181,38 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   const int P = L->tile_points;
   const dim3 tgrid((unsigned)L->ntiles, (unsigned)chunks);
   const int maxq = L->max_tile_runs;
+  SplatArgs<TU> sa;
+  sa.n = L->n;
+  sa.items = L->ntiles * chunks;
+  sa.P = P;
+  sa.D = D;
+  sa.C = C;
+  sa.chunks = chunks;
+  sa.vec_v = (TileShape<TU, G, kSplatBlock>::VEC && !perm && C == G && aligned16(V)) ? 1 : 0;
+  sa.cvec = (C % Vec16<TU>::N == 0 && aligned16(part)) ? 1 : 0;
+  sa.lds = splat_lds<TU>(P, D, L->max_tile_pieces, G);
+  // the previous CG iteration's direction update: in this splat where its
+  // values are whole vectors of all C columns, else as a pass of its own
+  const bool dir_fused = up && sizeof(TU) == 8 && TileShape<TU, G, kSplatBlock>::VEC && sa.vec_v;
+  if (up && !dir_fused) {
+    const int rc = launch_cg_dir(*up, (int64_t)L->n * C, C, s);
+    if (rc) return rc;
+  }
   {
     ProfScope ps(KK_SPLAT, s);
-    SplatArgs<TU> sa;
-    sa.n = L->n;
-    sa.items = L->ntiles * chunks;
-    sa.P = P;
-    sa.D = D;
-    sa.C = C;
-    sa.chunks = chunks;
-    sa.vec_v = (TileShape<TU, G, kSplatBlock>::VEC && !perm && C == G && aligned16(V)) ? 1 : 0;
-    sa.cvec = (C % Vec16<TU>::N == 0 && aligned16(part)) ? 1 : 0;
-    sa.lds = splat_lds<TU>(P, D, L->max_tile_pieces, G);
-    const unsigned grid =
-        persistent_grid((const void*)&k_splat_tile<TU, G>, kSplatBlock, sa.lds.total, sa.items, lc.splat_bpc);
-    hipLaunchKernelGGL((k_splat_tile<TU, G>), dim3(grid), dim3(kSplatBlock), sa.lds.total, s,
-                       (const int32_t*)L->stile_off.ptr, (const uint16_t*)L->run_rel.ptr,
-                       (const int32_t*)L->run_dst.ptr, (const uint8_t*)L->ent_lp.ptr,
-                       (const float*)L->ent_w.ptr, V, perm, part, sa);
+    const void* kern =
+        dir_fused ? (const void*)&k_splat_tile<TU, G, true> : (const void*)&k_splat_tile<TU, G, false>;
+    const unsigned grid = persistent_grid(kern, kSplatBlock, sa.lds.total, sa.items, lc.splat_bpc);
+    if (dir_fused)
+      hipLaunchKernelGGL((k_splat_tile<TU, G, true>), dim3(grid), dim3(kSplatBlock), sa.lds.total, s,
+                         (const int32_t*)L->stile_off.ptr, (const uint16_t*)L->run_rel.ptr,
+                         (const int32_t*)L->run_dst.ptr, (const uint8_t*)L->ent_lp.ptr,
+                         (const float*)L->ent_w.ptr, V, perm, part, sa, *up);
+    else
+      hipLaunchKernelGGL((k_splat_tile<TU, G, false>), dim3(grid), dim3(kSplatBlock), sa.lds.total, s,
+                         (const int32_t*)L->stile_off.ptr, (const uint16_t*)L->run_rel.ptr,
+                         (const int32_t*)L->run_dst.ptr, (const uint8_t*)L->ent_lp.ptr,
+                         (const float*)L->ent_w.ptr, V, perm, part, sa, CgDirUpdate{});
     SGP_LAUNCH_CHECK("k_splat_tile");
   }
   {
@@ -1285,12 +1348,17 @@ int chunk_lanes(const sgp_lattice* L, int C, size_t elem) {
   return g;
 }
 
+// work: the MVM's work memory (mvm_work_elems(L, C) elements of TU), or
+// null for the lattice's own buffer, grown on demand.
 template <typename TU>
 int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out,
-                 hipStream_t s, TU noise, const TU* p, const CgHook* hook) {
-  int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf,
-                       sizeof(TU) * (4 * L->m + L->npiece + 2 * gather_ranges(L)) * (size_t)C, s);
-  if (rc) return rc;
+                 hipStream_t s, TU noise, const TU* p, const CgHook* hook, void* work = nullptr,
+                 const CgDirUpdate* up = nullptr) {
+  if (!work) {
+    int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf, sizeof(TU) * mvm_work_elems(L, C), s);
+    if (rc) return rc;
+    work = L->ubuf.ptr;
+  }
   const int gmax = chunk_lanes(L, C, sizeof(TU));
   LaunchChoice lc{gmax, 0, 0};
   if (g_force)
@@ -1299,13 +1367,13 @@ int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C,
     (void)tune_find(L, C, (int)sizeof(TU), &lc);
   if (lc.g < 1 || lc.g > gmax || (lc.g & (lc.g - 1))) lc.g = gmax;  // never wider than the LDS allows
   switch (lc.g) {
-    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, hook, lc);
-    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, p, hook, lc);
-    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, p, hook, lc);
-    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, p, hook, lc);
-    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, p, hook, lc);
-    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, p, hook, lc);
-    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, p, hook, lc);
+    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
+    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
+    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
+    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
+    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
+    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
+    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
   }
 }
 
@@ -1316,9 +1384,9 @@ int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_
                                     nullptr);
 }
 
-int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t s, double noise,
-           const CgHook* hook) {
-  return mvm_dispatch<double>(L, p, nullptr, C, q, s, noise, p, hook);
+int mvm_cg(const sgp_lattice* L, double* p, int C, double* q, hipStream_t s, double noise,
+           const CgHook* hook, const CgDirUpdate* up) {
+  return mvm_dispatch<double>(L, p, nullptr, C, q, s, noise, p, hook, nullptr, up);
 }
 
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s) {
@@ -1448,5 +1516,6 @@ extern "C" int sgp_autotune(const sgp_lattice* L, int32_t C, int32_t fp64, int32
 
 extern "C" int sgp_autotune_reset(void) {
   autotune_reset();
+  build_tune_reset();
   return SGP_OK;
 }

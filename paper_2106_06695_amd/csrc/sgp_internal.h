@@ -72,6 +72,7 @@ bool profiling();
 // Process-wide switch for graph replay of CG iterations.
 bool cg_graphs_enabled();
 bool blur_fuse_enabled();
+bool cg_fuse_enabled();
 // A per-thread, per-device stream used only to record graphs.
 hipStream_t capture_stream();
 
@@ -211,12 +212,19 @@ size_t radix_tmp_words(int64_t count);
 template <typename K>
 int radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, int64_t count,
                      int bits, uint32_t* tmp, hipStream_t s, bool* result_in_alt);
+// Forget the build shapes sgp_autotune_build chose.
+void build_tune_reset();
 // fp32 values, fp32 lattice accumulation (lattice_mvm)
 int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s);
-// fp64 values and accumulation with the CG epilogue: q = A p, partial sums of p.q
+// fp64 values and accumulation with the CG epilogue: q = A p, partial sums
+// of p.q; up (may be null) is the previous iteration's direction update,
+// which the splat applies to p (in place) and x before splatting p
 struct CgHook;
-int mvm_cg(const sgp_lattice* L, const double* p, int C, double* q, hipStream_t s, double noise,
-           const CgHook* hook);
+struct CgDirUpdate;
+// The CG direction update as a pass of its own over the n x C arrays
+int launch_cg_dir(const CgDirUpdate& up, int64_t nC, int C, hipStream_t s);
+int mvm_cg(const sgp_lattice* L, double* p, int C, double* q, hipStream_t s, double noise,
+           const CgHook* hook, const CgDirUpdate* up);
 // fp64 values and accumulation, internal point order, no epilogue
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s);
 }  // namespace sgp

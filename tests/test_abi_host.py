@@ -51,7 +51,7 @@ def test_opts_defaults(lib):
     o = _lib.Opts()
     lib.sgp_opts_default(ctypes.byref(o))
     assert (o.order, o.kernel, o.blur) == (1, 0, 0)
-    assert o.outputscale == 1.0 and abs(o.load_factor - 0.5) < 1e-7
+    assert o.outputscale == 1.0 and o.load_factor == 0.0  # automatic table shape
 
 
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
@@ -80,7 +80,7 @@ def test_build_argument_errors(lib):
         assert rc == -1 and b"lengthscale 2" in lib.sgp_last_error()
     o = _lib.Opts()
     for field, value in (("order", 0), ("order", 9), ("kernel", 5), ("blur", 3),
-                         ("load_factor", 0.0), ("load_factor", 0.95), ("outputscale", float("inf"))):
+                         ("load_factor", -0.1), ("load_factor", 0.95), ("outputscale", float("inf"))):
         lib.sgp_opts_default(ctypes.byref(o))
         setattr(o, field, value)
         rc, _ = _build(lib, FAKE, 10, 4, pe, ctypes.byref(o))

@@ -511,3 +511,55 @@ def test_cg_graph_replay_matches_launches(sgp, tol, max_iter):
         lat.free()
     if tol > 0:
         assert np.all(it_ref > 20)  # several replayed blocks ran
+
+
+@pytest.mark.parametrize("seed,n,d,C,tol,max_iter", [(61, 20000, 6, 16, 0.0, 20), (62, 9000, 4, 4, 1e-5, 400),
+                                                     (63, 5000, 3, 5, 1e-4, 300), (64, 3000, 5, 1, 0.0, 13),
+                                                     (65, 12000, 7, 32, 0.0, 11), (66, 4000, 2, 8, 1e-6, 600)])
+def test_cg_fused_direction_update_matches_pass(sgp, seed, n, d, C, tol, max_iter):
+    """The CG direction update run inside the next splat gives bitwise the
+    same iterates, iteration counts and residuals as its own pass, with
+    columns that stop at different iterations, widths that take the fused
+    path (C = 4, 8, 16, 32) and widths that fall back to the pass (C = 1,
+    5), and graph replay on."""
+    _note(f"cg fused direction update seed={seed} n={n} d={d} C={C} tol={tol}")
+    c = workloads.small_case(seed, n, d, channels=C, kind="mixture")
+    lat = sgp.lattice_build(_cuda(c.X), c.lengthscales)
+    B = _cuda(c.values)
+    prev = sgp.cg_fuse_enable(False)
+    try:
+        x0, it0, rel0 = sgp.cg_solve(lat, B, 0.05, tol, max_iter=max_iter)
+        x0 = x0.cpu().numpy()
+        sgp.cg_fuse_enable(True)
+        for _ in range(2):
+            x1, it1, rel1 = sgp.cg_solve(lat, B, 0.05, tol, max_iter=max_iter)
+            np.testing.assert_array_equal(x1.cpu().numpy(), x0)
+            np.testing.assert_array_equal(it1, it0)
+            np.testing.assert_array_equal(rel1, rel0)
+    finally:
+        sgp.cg_fuse_enable(prev)
+        lat.free()
+
+
+def test_autotune_build_keeps_structure(sgp):
+    """Every hash-table shape the build autotuner tries, and the one it keeps,
+    give the same lattice bit for bit (numbering by first occurrence)."""
+    _note("build autotune")
+    c = workloads.small_case(67, 30000, 9, channels=1, kind="mixture")
+    X = _cuda(c.X)
+    sgp.autotune_reset()
+    try:
+        lat = sgp.lattice_build(X, c.lengthscales)
+        ref = sgp.lattice_export(lat)
+        lat.free()
+        ch = sgp.autotune_build(X, c.lengthscales, reps=1)
+        assert ch["load_factor"] in (0.25, 0.5, 0.9) and ch["shrink"] in (0, 2, 3, 4)
+        assert ch["ms_per_build"] > 0
+        for lf in (0.0, 0.25, 0.9):
+            lat = sgp.lattice_build(X, c.lengthscales, load_factor=lf)
+            got = sgp.lattice_export(lat)
+            lat.free()
+            for a, b in zip(ref, got):
+                np.testing.assert_array_equal(a, b)
+    finally:
+        sgp.autotune_reset()
