@@ -28,15 +28,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, cg: bool) -> float:
+def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, cg: bool,
+                 dir_frac: float = 0.0) -> float:
     """Algorithmic HBM bytes of ONE launch of a kernel kind: int32 indices,
     fp32 weights, every array touched once per launch. Inside CG (cg=True)
-    the values and lattice accumulators are fp64, in lattice_mvm fp32."""
+    the values and lattice accumulators are fp64, in lattice_mvm fp32.
+    dir_frac: the share of the splat launches that also apply the CG
+    direction update (r and x in, p and x out: 24 bytes per element)."""
     D, T = d + 1, 2 * r
     chains = 2 if sym else 1
     vb = ub = 8 if cg else 4
-    if kind == "splat":      # idx + w, V in, U out
-        return n * D * 8 + n * C * vb + m * C * ub
+    if kind == "splat":      # idx + w, V in, U out (+ the fused direction update)
+        return n * D * 8 + n * C * vb + m * C * ub + dir_frac * 24 * n * C
     if kind == "slice":      # idx + w, U (both chains) in, out (+ p in CG)
         return n * D * 8 + chains * m * C * ub + n * C * vb + (n * C * vb if cg else 0)
     if kind == "blur":       # average per launch: per chain U in, U out, neighbour lists
@@ -47,23 +50,27 @@ def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, c
         return 3 * n * C * 8 + 2 * n * C * 4
     if kind == "cg_init":    # b in (fp32); r, p out (fp64), x out (fp32)
         return n * C * 4 + 2 * n * C * 8 + n * C * 4
-    if kind == "cg_out":     # x in, x out (fp32)
-        return n * C * 8
+    if kind == "cg_out":     # x in, p in (the last x update), x out
+        return n * C * 16
     if kind == "fill":
         return m * C * ub
     return 0.0
 
 
-def survey_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool) -> float:
+def survey_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool,
+                 dir_frac: float = 0.0) -> float:
     """Algorithmic HBM bytes of ONE launch under the survey's byte model:
     fp32 values, int32 indices and fp32 weights whatever precision a kernel
     computes in, neighbour lists counted once per sweep. The splat stage is
     k_splat_tile + k_splat_gather + k_gather_fix; inside CG the slice also
-    reads the direction p once and every vector pass counts n*C*4 bytes."""
+    reads the direction p once, and every vector pass counts n*C*4 bytes
+    (the splat's fused direction update: r and x in, p and x out)."""
     D = d + 1
     chains = 2 if sym else 1
     if kind == "splat_stage":
-        return n * D * 8 + n * C * 4 + m * C * 4
+        return n * D * 8 + n * C * 4 + m * C * 4 + dir_frac * 16 * n * C
+    if kind == "splat":      # k_splat_tile alone: W and V in (U is the gather's)
+        return n * D * 8 + n * C * 4 + dir_frac * 16 * n * C
     if kind == "blur":
         return blur_bytes_per_mvm(d, m, C, r, sym, False) / blur_launches(d, r)
     if kind == "slice":      # CG variant: idx + w, U, out, and p
@@ -483,10 +490,12 @@ def main(argv=None):
         for _ in range(prof_steps):
             step()
         torch.cuda.synchronize()
+    # every splat but a solve's first applies the previous direction update
+    dir_frac = (iters - 1) / iters
     kernels = {}
     for kind, (launches, ms) in prof.results.items():
         if launches:
-            b = kernel_bytes(kind, n, d, m, C, 1, sym, cg=True)
+            b = kernel_bytes(kind, n, d, m, C, 1, sym, cg=True, dir_frac=dir_frac)
             avg = ms / launches
             kernels[kind] = {"launches": launches, "total_ms": round(ms, 3), "avg_us": round(avg * 1e3, 2),
                              "algo_GBps": round(b / (avg / 1e3) / 1e9, 1) if b else None}
@@ -508,18 +517,20 @@ def main(argv=None):
                 "achieved_operand_bytes": a_n, "frac_operand_bytes": a_n / HBM_PEAK_GBS,
                 "operand_bytes_per_launch": native_b}
 
-    names = {"splat": "k_splat_tile", "blur": "k_blur2_split / k_blur2", "slice": "k_slice_tile<double, G, true>",
+    names = {"splat": "k_splat_tile<double, G, true> (with the fused CG direction update)",
+             "blur": "k_blur2_split / k_blur2", "slice": "k_slice_tile<double, G, true>",
              "cg_update": "k_cg_update", "cg_dir": "k_cg_dir"}
     single = {k: kernels[k]["total_ms"] for k in names if k in kernels}
     dom = max(single, key=single.get)
-    splat_native = kernel_bytes("splat", n, d, m, C, 1, sym, cg=True)
-    dom_survey = {"splat": n * (d + 1) * 8 + n * C * 4}.get(dom, survey_bytes(dom, n, d, m, C, 1, sym))
-    dom_native = kernel_bytes(dom, n, d, m, C, 1, sym, cg=True)
+    splat_native = kernel_bytes("splat", n, d, m, C, 1, sym, cg=True, dir_frac=dir_frac)
+    dom_survey = survey_bytes(dom, n, d, m, C, 1, sym, dir_frac=dir_frac)
+    dom_native = kernel_bytes(dom, n, d, m, C, 1, sym, cg=True, dir_frac=dir_frac)
     if dom == "splat":  # the tile kernel alone reads W and V; U is written by the gather
         dom_native -= m * C * 8
     roofline = roof(names[dom], [dom], dom_survey, dom_native, dom)
     splat_stage = roof("k_splat_tile + k_splat_gather + k_gather_fix", ["splat", "splat_gather"],
-                       survey_bytes("splat_stage", n, d, m, C, 1, sym), splat_native, "splat_stage")
+                       survey_bytes("splat_stage", n, d, m, C, 1, sym, dir_frac=dir_frac), splat_native,
+                       "splat_stage")
 
     # standalone MVMs on a resident lattice (outside the timed steps)
     lat = sgp.lattice_build(X, w.lengthscales, blur=args.blur)
