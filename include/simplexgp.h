@@ -106,6 +106,25 @@ int lattice_build(const float* X, int64_t n, int32_t d, const double* lengthscal
  * Asynchronous on `stream`. */
 int lattice_mvm(const sgp_lattice* L, const float* values, int32_t C, float* out, void* stream);
 
+/* lattice_mvm for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operation, kernels and results as lattice_mvm, bit for bit, but
+ * the MVM's work memory (the lattice values, the splat's partial rows and
+ * fragments: 4 (4m + runs) C bytes, runs <= n(d+1)) is one fixed array of
+ * SGP_NOALLOC_SCRATCH_BYTES per device, part of the library's code object and
+ * held until the process ends. The call makes no device allocation and no
+ * allocating library call. The caller still passes values and out (n x C
+ * fp32, not overlapping). Every call on one device shares that device's
+ * array, and it keeps the last call's contents: calls that overlap in time on
+ * one device (different streams or threads) race and give wrong results;
+ * order them. The lattice's device must be current.
+ * Errors: SGP_EINVAL for NULL or overlapping arrays, C < 1, another device
+ * current, or work memory beyond SGP_NOALLOC_SCRATCH_BYTES (the message gives
+ * the size needed); SGP_EHIP if the array's device address is unavailable. */
+#define SGP_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int lattice_mvm_noalloc(const sgp_lattice* L, const float* values, int32_t C, float* out,
+                        void* stream);
+
 /* Conjugate gradients on (outputscale*K + noise*I) x = rhs, each of the C
  * columns an independent recurrence from x0 = 0 (Section 2, Krylov methods;
  * Section 5.4 for the tolerance semantics). A column stops when its

@@ -150,6 +150,21 @@ def lattice_mvm(lat: Lattice, values, out=None):
     return out
 
 
+def lattice_mvm_noalloc(lat: Lattice, values, out):
+    """lattice_mvm whose work memory is the library's fixed per-device
+    scratch array (no device allocation in the call); out must be given."""
+    pv = _dev_f32(values, "values", lat.n)
+    C = _cols(values)
+    po = _dev_f32(out, "out", lat.n)
+    if out.shape != values.shape:
+        raise ValueError("out must have the shape of values")
+    _check(_lib.load().lattice_mvm_noalloc(lat.handle, pv, C, po, _stream(values.device)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
 def cg_solve(lat: Lattice, rhs, noise: float, tol: float, max_iter: int = 500, x=None):
     """Solve (outputscale*K + noise*I) x = rhs per column by CG (Section 2).
     Returns (x, iterations per column, recursive relative residual per column)."""

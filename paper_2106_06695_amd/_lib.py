@@ -24,6 +24,7 @@ SIGNATURES = {
     "sgp_opts_default": (None, [_P]),
     "lattice_build": (ctypes.c_int, [_P, _I64, _I32, _P, _P, _P, _P]),
     "lattice_mvm": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
+    "lattice_mvm_noalloc": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
     "cg_solve": (ctypes.c_int, [_P, _P, _I32, _F, _F, _I32, _P, _P, _P, _P]),
     "lattice_mvm_grad": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P]),
     "lattice_info": (ctypes.c_int, [_P, _P, _P, _P, _P]),

@@ -1501,6 +1501,74 @@ extern "C" int lattice_mvm(const sgp_lattice* L, const float* values, int32_t C,
   return rc;
 }
 
+// Work memory of lattice_mvm_noalloc: one array per device, part of the
+// code object, held until the process ends. In host code `scratch` names a
+// host-side stand-in, not device memory: kernels receive the device address
+// that hipGetSymbolAddress returns for the current device, looked up once per
+// device on its first call.
+namespace {
+constexpr size_t kScratchBytes = (size_t)SGP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kScratchDevices] = {};
+
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      set_error("lattice_mvm_noalloc: no device address for the scratch array on device %d: %s", dev,
+                hipGetErrorString(e));
+      return SGP_EHIP;
+    }
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return SGP_OK;
+}
+}  // namespace
+
+extern "C" int lattice_mvm_noalloc(const sgp_lattice* L, const float* values, int32_t C, float* out,
+                                   void* stream) {
+  if (!L || !values || !out) {
+    set_error("lattice_mvm_noalloc: NULL argument");
+    return SGP_EINVAL;
+  }
+  if (C < 1) {
+    set_error("lattice_mvm_noalloc: C must be >= 1 (got %d)", (int)C);
+    return SGP_EINVAL;
+  }
+  const size_t bytes = sizeof(float) * (size_t)L->n * (size_t)C;
+  const char* v0 = (const char*)values;
+  const char* o0 = (const char*)out;
+  if (v0 < o0 + bytes && o0 < v0 + bytes) {
+    set_error("lattice_mvm_noalloc: out overlaps values");
+    return SGP_EINVAL;
+  }
+  const size_t need = sizeof(float) * mvm_work_elems(L, C);
+  if (need > kScratchBytes) {
+    set_error("lattice_mvm_noalloc: this lattice and C = %d need %zu bytes of work memory; the "
+              "no-allocation entry point has %zu (use lattice_mvm)", (int)C, need, kScratchBytes);
+    return SGP_EINVAL;
+  }
+  int dev = 0;
+  SGP_HIP(hipGetDevice(&dev));
+  if (dev != L->device || dev < 0 || dev >= kScratchDevices) {
+    set_error("lattice_mvm_noalloc: make the lattice's device (%d) current (current: %d)", L->device, dev);
+    return SGP_EINVAL;
+  }
+  void* work = nullptr;
+  int rc = scratch_address(dev, &work);
+  if (rc) return rc;
+  rc = mvm_dispatch<float>(L, values, (const uint32_t*)L->perm.ptr, C, out, (hipStream_t)stream, 0.f,
+                           nullptr, nullptr, work);
+  if (rc == SGP_OK) mark_use(L, (hipStream_t)stream);
+  return rc;
+}
+
 extern "C" int sgp_autotune(const sgp_lattice* L, int32_t C, int32_t fp64, int32_t reps, void* stream,
                             int32_t* choice, float* ms_per_mvm) {
   if (!L) {
