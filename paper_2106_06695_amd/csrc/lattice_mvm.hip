@@ -303,8 +303,12 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
             // C == G here: element f of the tile is column f % G of row f / G
             typedef float fvN __attribute__((ext_vector_type(N)));
             const int64_t e = p0 * a.C + f;
-            const typename Vec16<TU>::T r2 = *(const typename Vec16<TU>::T*)((const TU*)up.r + e);
-            const fvN x2 = *(const fvN*)(up.x + e);
+            // r and x are read once here and p, x next read by other
+            // kernels: streamed past the caches (non-temporal), which keeps
+            // the partial rows that the gather reads next in them
+            const typename Vec16<TU>::T r2 =
+                __builtin_nontemporal_load((const typename Vec16<TU>::T*)((const TU*)up.r + e));
+            const fvN x2 = __builtin_nontemporal_load((const fvN*)(up.x + e));
             typename Vec16<TU>::T pn;
             fvN xn;
 #pragma unroll
@@ -314,8 +318,8 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
               xn[j] = (float)__builtin_fma(s_alpha[c], (double)pold, (double)x2[j]);
               pn[j] = s_active[c] ? (TU)__builtin_fma(s_beta[c], (double)pold, (double)r2[j]) : pold;
             }
-            *(typename Vec16<TU>::T*)((TU*)up.p + e) = pn;
-            *(fvN*)(up.x + e) = xn;
+            __builtin_nontemporal_store(pn, (typename Vec16<TU>::T*)((TU*)up.p + e));
+            __builtin_nontemporal_store(xn, (fvN*)(up.x + e));
             x = pn;
           } else {
 #pragma unroll
@@ -430,15 +434,18 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 // the range; slot 1: it ends the range), summed in range order by
 // k_gather_fix. The work per group is fixed, whatever the list lengths.
 constexpr int kGatherRows = 64;
-template <typename TU, int G>
+// VW channels per lane (16-byte loads when the rows allow), G / VW lanes per
+// group; every channel's rows are added in the same order for any VW.
+template <typename TU, int G, int VW>
 __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restrict__ row_vert,
                                                          const TU* __restrict__ part,
                                                          TU* __restrict__ U, TU* __restrict__ frag,
                                                          int64_t nrows, int C, int64_t ngroups) {
-  constexpr int GPB = kBlock / G;  // groups per block
-  constexpr int B = 8;             // rows loaded together
-  const int lane = threadIdx.x % G;
-  const int64_t gi = xcd_block(blockIdx.x, gridDim.x) * GPB + threadIdx.x / G;
+  constexpr int LG = G / VW;       // lanes per group
+  constexpr int GPB = kBlock / LG;  // groups per block
+  constexpr int B = 8;              // rows loaded together
+  const int lane = threadIdx.x % LG;
+  const int64_t gi = xcd_block(blockIdx.x, gridDim.x) * GPB + threadIdx.x / LG;
   if (gi >= ngroups) return;
   const int64_t o0 = gi * kGatherRows;
   const int64_t o1 = o0 + kGatherRows < nrows ? o0 + kGatherRows : nrows;
@@ -446,24 +453,24 @@ __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restri
   // its lattice point continues across
   const int32_t before = o0 > 0 ? row_vert[o0 - 1] : -1;
   const int32_t after = o1 < nrows ? row_vert[o1] : -1;
-  for (int c = lane; c < C; c += G) {
+  for (int c = lane * VW; c < C; c += G) {
     int32_t cur = row_vert[o0];
     int64_t seg = o0;
-    TU acc = 0;
+    TU acc[VW];
+#pragma unroll
+    for (int i = 0; i < VW; ++i) acc[i] = 0;
     auto flush = [&](int64_t end) {
       const bool whole = (seg > o0 || before != cur) && (end < o1 || after != cur);
-      if (whole)
-        U[(int64_t)cur * C + c] = acc;
-      else
-        frag[(gi * 2 + (seg == o0 ? 0 : 1)) * C + c] = acc;
+      TU* dst = whole ? U + (int64_t)cur * C + c : frag + (gi * 2 + (seg == o0 ? 0 : 1)) * C + c;
+      write_row<TU, VW>(dst, acc);
     };
     for (int64_t k0 = o0; k0 < o1; k0 += B) {
-      TU v[B];
+      TU v[B][VW];
       int32_t rv[B];
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int64_t k = k0 + u < o1 ? k0 + u : o1 - 1;
-        v[u] = part[k * C + c];
+        read_row<TU, VW>(part + k * C + c, v[u]);
         rv[u] = row_vert[k];
       }
 #pragma unroll
@@ -473,9 +480,11 @@ __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restri
             flush(k0 + u);
             cur = rv[u];
             seg = k0 + u;
-            acc = 0;
+#pragma unroll
+            for (int i = 0; i < VW; ++i) acc[i] = 0;
           }
-          acc += v[u];
+#pragma unroll
+          for (int i = 0; i < VW; ++i) acc[i] += v[u][i];
         }
       }
     }
@@ -1218,9 +1227,16 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   {
     ProfScope ps(KK_SPLAT_GATHER, s);
     const int64_t ngroups = (L->npiece + kGatherRows - 1) / kGatherRows;
-    const int64_t blocks = (ngroups + kBlock / G - 1) / (kBlock / G);
-    hipLaunchKernelGGL((k_splat_gather<TU, G>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                       (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups);
+    constexpr int VWG = 16 / (int)sizeof(TU);  // channels per lane with 16-byte loads
+    if (G % VWG == 0 && C % VWG == 0 && aligned16(part) && aligned16(U0) && aligned16(frag)) {
+      const int64_t blocks = (ngroups + kBlock / (G / VWG) - 1) / (kBlock / (G / VWG));
+      hipLaunchKernelGGL((k_splat_gather<TU, G, (G % VWG == 0 ? VWG : 1)>), dim3((unsigned)blocks), dim3(kBlock),
+                         0, s, (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups);
+    } else {
+      const int64_t blocks = (ngroups + kBlock / G - 1) / (kBlock / G);
+      hipLaunchKernelGGL((k_splat_gather<TU, G, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                         (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups);
+    }
     SGP_LAUNCH_CHECK("k_splat_gather");
     hipLaunchKernelGGL(k_gather_fix, dim3(grid_cap(ngroups * C)), dim3(kBlock), 0, s,
                        (const int32_t*)L->row_vert.ptr, (const int32_t*)L->occ_ptr.ptr, (const void*)frag,
