@@ -124,15 +124,32 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ r,
   extern __shared__ double dsh[];
   cg_partials<kSuperUpdate>(n, C, partials, dsh, [=](int64_t i0, int c) {
     const double a = st->alpha[c];
-    // all loads of the group first, then the stores
+    // all loads of the group first, then the stores; a whole group (every
+    // group but possibly the last) has no per-row branches, which would make
+    // each store wait for the one before it
     double qv[kCgRowsPerGroup], rv[kCgRowsPerGroup];
+    double dot = 0.0;
+    if (i0 + kCgRowsPerGroup <= n) {
+#pragma unroll
+      for (int k = 0; k < kCgRowsPerGroup; ++k) {
+        const int64_t e = (i0 + k) * C + c;
+        qv[k] = q_[e];
+        rv[k] = r[e];
+      }
+#pragma unroll
+      for (int k = 0; k < kCgRowsPerGroup; ++k) {
+        const double v = __builtin_fma(-a, qv[k], rv[k]);
+        r[(i0 + k) * C + c] = v;
+        dot += v * v;
+      }
+      return dot;
+    }
 #pragma unroll
     for (int k = 0; k < kCgRowsPerGroup; ++k) {
       const int64_t e = (i0 + k) * C + c;
       qv[k] = i0 + k < n ? q_[e] : 0.0;
       rv[k] = i0 + k < n ? r[e] : 0.0;
     }
-    double dot = 0.0;
 #pragma unroll
     for (int k = 0; k < kCgRowsPerGroup; ++k) {
       if (i0 + k < n) {

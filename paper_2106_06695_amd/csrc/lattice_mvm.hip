@@ -101,6 +101,24 @@ __device__ __forceinline__ void write_row(T* p, const T (&v)[W]) {
   }
 }
 
+// write_row with non-temporal stores (streamed past the caches)
+template <typename TU, int W>
+__device__ __forceinline__ void write_row_nt(TU* p, const TU (&v)[W]) {
+  constexpr int N = Vec16<TU>::N;
+  if constexpr (W % N == 0) {
+#pragma unroll
+    for (int i = 0; i < W / N; ++i) {
+      typename Vec16<TU>::T x;
+#pragma unroll
+      for (int j = 0; j < N; ++j) x[j] = v[i * N + j];
+      __builtin_nontemporal_store(x, (typename Vec16<TU>::T*)(p + i * N));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; ++i) __builtin_nontemporal_store(v[i], p + i);
+  }
+}
+
 // Persistent tile kernels: block b runs on XCD b % 8 and takes work items
 // from a contiguous range owned by its XCD, striding over it with the other
 // blocks of that XCD.
@@ -537,6 +555,7 @@ struct BlurArgs {
   int chains;
   int sum_out;  // last SYMMETRIC step: out[0] = forward + reverse
   int vec;      // rows of C channels start 16-byte aligned
+  int nt;       // lattice values exceed the Infinity Cache: stream the outputs past it
   int64_t rows_per_block;
   TU st[2 * kMaxOrder + 1];
 };
@@ -544,11 +563,29 @@ struct BlurArgs {
 // One chain's blur of VW channels of row j: sum over t = -r..r of
 // stencil[t] * U[neighbour(j, t)], in t order; a missing neighbour adds 0.
 template <typename TU, int VW>
+__device__ __forceinline__ void load_vw(const TU* __restrict__ in, int64_t row, int64_t valid, int C, int c,
+                                        bool vec, TU (&v)[VW]);
+
+template <typename TU, int VW>
 __device__ __forceinline__ void blur_rows(const TU* __restrict__ in, const int32_t* __restrict__ nb,
                                           int64_t m, int64_t j, int C, int c, int r, const TU* st,
                                           bool vec, TU (&acc)[VW]) {
 #pragma unroll
   for (int i = 0; i < VW; ++i) acc[i] = 0;
+  if (r == 1) {
+    // the three-tap stencil: both neighbour indices, then the three rows, in
+    // flight together
+    const int64_t lo = nb[j], hi = nb[m + j];
+    TU v[3][VW];
+    load_vw<TU, VW>(in, lo, j, C, c, vec, v[0]);
+    load_vw<TU, VW>(in, j, j, C, c, vec, v[1]);
+    load_vw<TU, VW>(in, hi, j, C, c, vec, v[2]);
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int i = 0; i < VW; ++i) acc[i] = fma_t(st[t], v[t][i], acc[i]);
+    return;
+  }
   // neighbour rows first (2r independent loads), then the values
   int32_t nbv[2 * kMaxOrder];
   for (int ti = 0; ti < 2 * r; ++ti) nbv[ti] = nb[(int64_t)ti * m + j];
@@ -556,18 +593,7 @@ __device__ __forceinline__ void blur_rows(const TU* __restrict__ in, const int32
   for (int t = -r; t <= r; ++t) {
     const int64_t row = t == 0 ? j : (int64_t)nbv[ti++];
     TU v[VW];
-    if (row >= 0) {
-      const TU* src = in + row * C + c;
-      if (vec) {
-        read_row<TU, VW>(src, v);
-      } else {
-#pragma unroll
-        for (int i = 0; i < VW; ++i) v[i] = c + i < C ? src[i] : (TU)0;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < VW; ++i) v[i] = 0;
-    }
+    load_vw<TU, VW>(in, row, j, C, c, vec, v);
 #pragma unroll
     for (int i = 0; i < VW; ++i) acc[i] = fma_t(st[t + r], v[i], acc[i]);
   }
@@ -599,7 +625,10 @@ __global__ __launch_bounds__(kBlock) void k_blur(BlurArgs<TU> a) {
         } else {
           TU* o1 = a.out[1] + j * a.C + c;
           if (vec) {
-            write_row<TU, VW>(o1, b);
+            if (a.nt)
+              write_row_nt<TU, VW>(o1, b);
+            else
+              write_row<TU, VW>(o1, b);
           } else {
 #pragma unroll
             for (int i = 0; i < VW; ++i)
@@ -609,7 +638,10 @@ __global__ __launch_bounds__(kBlock) void k_blur(BlurArgs<TU> a) {
       }
       TU* o0 = a.out[0] + j * a.C + c;
       if (vec) {
-        write_row<TU, VW>(o0, f);
+        if (a.nt)
+          write_row_nt<TU, VW>(o0, f);
+        else
+          write_row<TU, VW>(o0, f);
       } else {
 #pragma unroll
         for (int i = 0; i < VW; ++i)
@@ -637,25 +669,30 @@ struct Blur2Args {
   int sum_out;
   int split;  // two chains with outputs of their own: the grid's halves take one each
   int vec;
+  int nt;     // as in BlurArgs
   int64_t rows_per_block;
   TU st[3];
 };
 
+// VW values of a lattice row, or zeros where row < 0 (a missing neighbour).
+// The load is issued unconditionally (from row `valid` when row < 0) and the
+// zeros selected afterwards, so a thread's loads never wait on one another
+// through a branch.
 template <typename TU, int VW>
-__device__ __forceinline__ void load_vw(const TU* __restrict__ in, int64_t row, int C, int c, bool vec,
-                                        TU (&v)[VW]) {
-  if (row >= 0) {
-    const TU* src = in + row * C + c;
-    if (vec) {
-      read_row<TU, VW>(src, v);
-    } else {
-#pragma unroll
-      for (int i = 0; i < VW; ++i) v[i] = c + i < C ? src[i] : (TU)0;
-    }
+__device__ __forceinline__ void load_vw(const TU* __restrict__ in, int64_t row, int64_t valid, int C, int c,
+                                        bool vec, TU (&v)[VW]) {
+  const TU* src = in + (row >= 0 ? row : valid) * C + c;
+  if (vec) {
+    read_row<TU, VW>(src, v);
   } else {
 #pragma unroll
-    for (int i = 0; i < VW; ++i) v[i] = 0;
+    for (int i = 0; i < VW; ++i) {
+      const TU x = src[c + i < C ? i : 0];
+      v[i] = c + i < C ? x : (TU)0;
+    }
   }
+#pragma unroll
+  for (int i = 0; i < VW; ++i) v[i] = row >= 0 ? v[i] : (TU)0;
 }
 
 template <typename TU, int VW>
@@ -668,18 +705,22 @@ __device__ __forceinline__ void blur2_rows(const TU* __restrict__ in, const int3
   x[0] = nb2[j];
   x[1] = j;
   x[2] = nb2[m + j];
+  // (all six index loads and all nine row loads issue without waiting on
+  // one another: indices of a missing x are read at j and discarded)
   int64_t y[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    y[a][0] = x[a] >= 0 ? (int64_t)nb1[x[a]] : -1;
+    const int64_t xa = x[a] >= 0 ? x[a] : j;
+    const int32_t lo = nb1[xa], hi = nb1[m + xa];
+    y[a][0] = x[a] >= 0 ? (int64_t)lo : -1;
     y[a][1] = x[a];
-    y[a][2] = x[a] >= 0 ? (int64_t)nb1[m + x[a]] : -1;
+    y[a][2] = x[a] >= 0 ? (int64_t)hi : -1;
   }
   TU v[3][3][VW];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) load_vw<TU, VW>(in, y[a][b], C, c, vec, v[a][b]);
+    for (int b = 0; b < 3; ++b) load_vw<TU, VW>(in, y[a][b], j, C, c, vec, v[a][b]);
 #pragma unroll
   for (int i = 0; i < VW; ++i) acc[i] = 0;
 #pragma unroll
@@ -720,7 +761,10 @@ __global__ __launch_bounds__(kBlock) void k_blur2(Blur2Args<TU> a) {
         } else {
           TU* o1 = a.out[1] + j * a.C + c;
           if (vec) {
-            write_row<TU, VW>(o1, b);
+            if (a.nt)
+              write_row_nt<TU, VW>(o1, b);
+            else
+              write_row<TU, VW>(o1, b);
           } else {
 #pragma unroll
             for (int i = 0; i < VW; ++i)
@@ -730,7 +774,10 @@ __global__ __launch_bounds__(kBlock) void k_blur2(Blur2Args<TU> a) {
       }
       TU* o0 = a.out[0] + j * a.C + c;
       if (vec) {
-        write_row<TU, VW>(o0, f);
+        if (a.nt)
+          write_row_nt<TU, VW>(o0, f);
+        else
+          write_row<TU, VW>(o0, f);
       } else {
 #pragma unroll
         for (int i = 0; i < VW; ++i)
@@ -761,7 +808,10 @@ __global__ __launch_bounds__(kBlock) void k_blur2_split(Blur2Args<TU> a) {
       blur2_rows<TU, VW>(a.in[chain], a.nbr1[chain], a.nbr2[chain], a.m, j, a.C, c, a.st, vec, f);
       TU* o = a.out[chain] + j * a.C + c;
       if (vec) {
-        write_row<TU, VW>(o, f);
+        if (a.nt)
+          write_row_nt<TU, VW>(o, f);
+        else
+          write_row<TU, VW>(o, f);
       } else {
 #pragma unroll
         for (int i = 0; i < VW; ++i)
@@ -1254,6 +1304,9 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   unsigned bblocks;
   split_rows(m, kBlock / (G / blur_vw<G>()), 65536, &bblocks, &a.rows_per_block);
   a.vec = (C % Vec16<TU>::N == 0 && blur_vw<G>() % Vec16<TU>::N == 0 && aligned16(U0)) ? 1 : 0;
+  // when the four lattice value arrays outgrow the 256 MiB Infinity Cache, the
+  // blur's outputs stream past it, which keeps more of its inputs cached
+  a.nt = (4.0 * (double)mC * sizeof(TU) > 256.0 * (1 << 20)) ? 1 : 0;
   const int32_t* nbr = (const int32_t*)L->nbr.ptr;
   // Chain 0 moves between B1 and B3 and never writes U0, which chain 1 reads
   // first; chain 1 moves between B2 and U0. Steps run in fused pairs when
@@ -1284,6 +1337,7 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
       b2.sum_out = (sym && step + 1 == d) ? 1 : 0;
       b2.split = (a.chains == 2 && !b2.sum_out) ? 1 : 0;
       b2.vec = a.vec;
+      b2.nt = a.nt;
       b2.rows_per_block = a.rows_per_block;
       for (int t = 0; t < 3; ++t) b2.st[t] = a.st[t];
       {
