@@ -261,6 +261,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_out(const float* __restrict__ xs,
   }
 }
 
+// The last solve's idle graph on this thread (a plain thread-local pair, so
+// nothing runs at thread or process exit).
+thread_local hipGraph_t t_idle_graph = nullptr;
+thread_local hipGraphExec_t t_idle_exec = nullptr;
+
+void retire_graphs() {
+  if (t_idle_exec) (void)hipGraphExecDestroy(t_idle_exec);
+  if (t_idle_graph) (void)hipGraphDestroy(t_idle_graph);
+  t_idle_exec = nullptr;
+  t_idle_graph = nullptr;
+}
+
+void defer_graph(hipGraph_t g, hipGraphExec_t e) {
+  retire_graphs();
+  t_idle_graph = g;
+  t_idle_exec = e;
+}
+
 template <int G>
 int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, int max_iter,
          float* x, int32_t* iters, float* rel, hipStream_t s) {
@@ -366,26 +384,36 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   }
   if (!done && polling && it < max_iter && it % blk != 0)
     if ((rc = all_done(&done))) return rc;
+  // Tearing a graph down costs the host a few hundred microseconds. A
+  // solve's graph is kept until the next solve on this thread has put its
+  // first iterations on the GPU and is torn down then, so the GPU does not
+  // wait for it; if the function returns early, it is torn down at once.
+  retire_graphs();
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct GraphGuard {
+    hipGraph_t* g;
+    hipGraphExec_t* e;
+    hipStream_t s;
+    bool keep = false;
+    ~GraphGuard() {
+      if (keep) {
+        defer_graph(*g, *e);
+        return;
+      }
+      if (*e) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(*e);
+      }
+      if (*g) (void)hipGraphDestroy(*g);
+    }
+  } guard{&graph, &exec, s};
   if (!done && max_iter - it >= 2 * blk && cg_graphs_enabled() && !profiling()) {
     hipStream_t cs = capture_stream();
     if (!cs) {
       set_error("cg_solve: could not create a capture stream");
       return SGP_EHIP;
     }
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    struct GraphGuard {
-      hipGraph_t* g;
-      hipGraphExec_t* e;
-      hipStream_t s;
-      ~GraphGuard() {
-        if (*e) {
-          (void)hipStreamSynchronize(s);
-          (void)hipGraphExecDestroy(*e);
-        }
-        if (*g) (void)hipGraphDestroy(*g);
-      }
-    } guard{&graph, &exec, s};
     SGP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int crc = SGP_OK;
     for (int b = 0; b < blk && !crc; ++b) crc = iterate(cs, false);
@@ -417,6 +445,7 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   SGP_HIP(hipMemcpyAsync(host, st->iters, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
   SGP_HIP(hipMemcpyAsync(host + kMaxCgCols, st->rel, sizeof(float) * C, hipMemcpyDeviceToHost, s));
   SGP_HIP(hipStreamSynchronize(s));
+  guard.keep = true;  // idle now: torn down during the next solve
   mark_use(L, s);
   for (int c = 0; c < C; ++c) {
     if (iters) iters[c] = host[c];
