@@ -41,7 +41,8 @@ enum BuildFlag : uint32_t {
   BF_NONFINITE = 1u,
   BF_OVERFLOW = 2u,
   BF_TABLE_FULL = 4u,
-  BF_COLLISION = 8u
+  BF_COLLISION = 8u,
+  BF_ORDER = 16u  // a tile's sorted order names an entry past the tile (internal error)
 };
 
 constexpr unsigned long long kEmpty = 0ull;
@@ -522,9 +523,8 @@ __device__ __forceinline__ int tile_at(int i) { return (i & (kTileSpan - 1)) * k
 
 struct TileSort {
   unsigned long long key[kTileSlots];  // at tile_at(position)
-  int32_t rstart[kTileSlots];  // sorted position of each run's first entry
+  int32_t rstart[kTileSlots];  // sorted position of each run's first entry (first the radix counters)
   int32_t wsum[kTileThreads / 64];
-  unsigned long long wsum64[kTileThreads / 64];
 };
 
 // Block-wide exclusive scan of one count per thread; *total gets the sum.
@@ -548,61 +548,70 @@ __device__ inline int tile_scan(int v, int32_t* wsum, int* total) {
   return before + x - v;
 }
 
-// Block-wide exclusive scan of one 64-bit value per thread (packed
-// counters that do not carry into each other); *total gets the sum.
-__device__ inline unsigned long long tile_scan64(unsigned long long v, unsigned long long* wsum,
-                                                 unsigned long long* total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  unsigned long long x = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned long long y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) wsum[w] = x;
-  __syncthreads();
-  unsigned long long before = 0, all = 0;
-  for (int i = 0; i < kTileThreads / 64; ++i) {
-    const unsigned long long c = wsum[i];
-    before += i < w ? c : 0;
-    all += c;
-  }
-  __syncthreads();
-  *total = all;
-  return before + x - v;
-}
-
 // Stable LSD radix sort of all kTileSlots keys by their lattice-point field
-// (key >> 12; entries past the tile hold ~0 and stay last), two bits per
-// pass. The four bucket counts of a thread's keys travel as 13-bit fields
-// of one 64-bit word through one block scan. key[] holds the keys in entry
-// order on entry and sorted on exit.
-__device__ inline void tile_radix(unsigned long long* key, unsigned long long* wsum, int bits) {
-  const int i0 = threadIdx.x * kTileSpan;
+// (key >> 12; entries past the tile hold ~0 and stay last), kRadixBits bits
+// per pass. In a pass thread t holds positions t + u * kTileThreads (rounds
+// u = 0..3). A key's rank among the keys of its wave and round with the
+// same digit comes from the lanes' ballots of the digit bits; the counts
+// per (digit, round, wave), scanned in that order, give every group its
+// first position, so keys with equal digits keep their order. key[] holds
+// the keys in entry order at tile_at(entry) on entry and the sorted keys
+// at tile_at(position) on exit; hist takes kTileSlots counters.
+constexpr int kRadixBits = 6;
+static_assert((1 << kRadixBits) * kTileSpan * (kTileThreads / 64) == kTileSlots, "radix counters");
+__device__ inline void tile_radix(unsigned long long* key, int32_t* hist, int32_t* wsum, int bits) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const unsigned long long below = (1ull << lane) - 1;
   unsigned long long v[kTileSpan];
 #pragma unroll
-  for (int u = 0; u < kTileSpan; ++u) v[u] = key[tile_at(i0 + u)];
-  for (int b = 0; b < bits; b += 2) {
-    int dg[kTileSpan];
-    unsigned long long cnt = 0;
+  for (int u = 0; u < kTileSpan; ++u) v[u] = key[tile_at(t + u * kTileThreads)];
+  for (int b = 0; b < bits; b += kRadixBits) {
+    const int nb = bits - b < kRadixBits ? bits - b : kRadixBits;
+    const bool last = b + nb >= bits;
+#pragma unroll
+    for (int k = 0; k < kTileSpan; ++k) hist[t * kTileSpan + k] = 0;
+    __syncthreads();
+    int dg[kTileSpan], rk[kTileSpan];
 #pragma unroll
     for (int u = 0; u < kTileSpan; ++u) {
-      dg[u] = (int)((v[u] >> (12 + b)) & 3u);
-      cnt += 1ull << (13 * dg[u]);
+      dg[u] = (int)((v[u] >> (12 + b)) & ((1u << nb) - 1));
+      unsigned long long peers = ~0ull;  // lanes whose digit equals this lane's
+#pragma unroll
+      for (int k = 0; k < kRadixBits; ++k) {
+        if (k < nb) {
+          const bool set = (dg[u] >> k) & 1;
+          const unsigned long long bal = __ballot(set);
+          peers &= set ? bal : ~bal;
+        }
+      }
+      rk[u] = (int)__popcll(peers & below);
+      if (rk[u] == 0) hist[(dg[u] * kTileSpan + u) * (kTileThreads / 64) + w] = (int)__popcll(peers);
     }
-    unsigned long long tot;
-    unsigned long long run = tile_scan64(cnt, wsum, &tot);
-    const int t0 = (int)(tot & 8191u), t1 = (int)((tot >> 13) & 8191u), t2 = (int)((tot >> 26) & 8191u);
-    const int bucket0[4] = {0, t0, t0 + t1, t0 + t1 + t2};
+    __syncthreads();
+    int h[kTileSpan], sum = 0;
 #pragma unroll
-    for (int u = 0; u < kTileSpan; ++u) {
-      const int pos = bucket0[dg[u]] + (int)((run >> (13 * dg[u])) & 8191u);
-      run += 1ull << (13 * dg[u]);
-      key[tile_at(pos)] = v[u];
+    for (int k = 0; k < kTileSpan; ++k) {
+      h[k] = hist[t * kTileSpan + k];
+      sum += h[k];
+    }
+    int tot;
+    int pre = tile_scan(sum, wsum, &tot);  // every thread has read its counters
+#pragma unroll
+    for (int k = 0; k < kTileSpan; ++k) {
+      hist[t * kTileSpan + k] = pre;
+      pre += h[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kTileSpan; ++u) v[u] = key[tile_at(i0 + u)];
+    for (int u = 0; u < kTileSpan; ++u) {
+      const int pos = hist[(dg[u] * kTileSpan + u) * (kTileThreads / 64) + w] + rk[u];
+      key[last ? tile_at(pos) : pos] = v[u];
+    }
     __syncthreads();
+    if (!last) {
+#pragma unroll
+      for (int u = 0; u < kTileSpan; ++u) v[u] = key[t + u * kTileThreads];
+    }
   }
 }
 
@@ -675,7 +684,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     T.key[tile_at(i)] = i < ne ? ((unsigned long long)(uint32_t)pm[base + i].j << 12) | (unsigned)i : ~0ull;
   }
   __syncthreads();
-  tile_radix(T.key, T.wsum64, mbits);
+  tile_radix(T.key, T.rstart, T.wsum, mbits);  // rstart is free until the ranks
   TileRanks r;
   tile_ranks(T, ne, K, r);
   // Positions whose key is compared with the stored key: the first entry of
@@ -726,11 +735,17 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(8)
     for (int l = 0; l < d; ++l) bad |= key[l] != vertex_coord(pt_r0, pt_rank, pt, d, kv, l);
   }
   if (bad) atomicOr(flags, BF_COLLISION);
+  bool stray = false;
 #pragma unroll
   for (int u = 0; u < kTileSpan; ++u) {
     const int i = threadIdx.x * kTileSpan + u;
-    if (i < ne) ord[base + i] = (uint16_t)(T.key[tile_at(i)] & 4095u);
+    if (i < ne) {
+      const int le = (int)(T.key[tile_at(i)] & 4095u);
+      stray |= le >= ne;
+      ord[base + i] = (uint16_t)(le < ne ? le : 0);  // never send the next pass past the tile
+    }
   }
+  if (stray) atomicOr(flags, BF_ORDER);
   if (threadIdx.x == 0) {
     runs[t] = (uint32_t)r.runs;
     pieces[t] = (uint32_t)r.pieces;
@@ -1381,6 +1396,10 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   SGP_HIP(hipMemcpyAsync(host_word, words, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost, st));
   SGP_HIP(hipStreamSynchronize(st));
   tr.idle = true;  // every kernel of this attempt has finished
+  if (host_word[0] & BF_ORDER) {
+    set_error("lattice_build: internal error, a tile's sorted order is not a permutation");
+    return SGP_EHASH;
+  }
   if (host_word[0] & BF_COLLISION) *retry = true;
   if (!*retry && (int64_t)host_word[2] != m) {
     set_error("lattice_build: internal numbering found %u lattice points, expected %lld",
