@@ -40,12 +40,12 @@ def kernel_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool, c
     vb = ub = 8 if cg else 4
     if kind == "splat":      # idx + w, V in, U out (+ the fused direction update)
         return n * D * 8 + n * C * vb + m * C * ub + dir_frac * 24 * n * C
-    if kind == "slice":      # idx + w, U (both chains) in, out (+ p in CG)
-        return n * D * 8 + chains * m * C * ub + n * C * vb + (n * C * vb if cg else 0)
+    if kind == "slice":      # idx + w, U (both chains) in, out (+ p and r in inside CG, out being r)
+        return n * D * 8 + chains * m * C * ub + n * C * vb + (2 * n * C * vb if cg else 0)
     if kind == "blur":       # average per launch: per chain U in, U out, neighbour lists
         return blur_bytes_per_mvm(d, m, C, r, sym, cg) / blur_launches(d, r)
-    if kind == "cg_update":  # q, r in; r out (fp64)
-        return 3 * n * C * 8
+    if kind == "cg_alpha":   # u and B u in (fp64)
+        return 2 * m * C * 8
     if kind == "cg_dir":     # p, r in (fp64), x in (fp32); p out (fp64), x out (fp32)
         return 3 * n * C * 8 + 2 * n * C * 4
     if kind == "cg_init":    # b in (fp32); r, p out (fp64), x out (fp32)
@@ -63,8 +63,9 @@ def survey_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool,
     fp32 values, int32 indices and fp32 weights whatever precision a kernel
     computes in, neighbour lists counted once per sweep. The splat stage is
     k_splat_tile + k_splat_gather + k_gather_fix; inside CG the slice also
-    reads the direction p once, and every vector pass counts n*C*4 bytes
-    (the splat's fused direction update: r and x in, p and x out)."""
+    reads the direction p and moves the residual r (in and out), and every
+    vector pass counts n*C*4 bytes (the splat's fused direction update: r and
+    x in, p and x out)."""
     D = d + 1
     chains = 2 if sym else 1
     if kind == "splat_stage":
@@ -73,10 +74,10 @@ def survey_bytes(kind: str, n: int, d: int, m: int, C: int, r: int, sym: bool,
         return n * D * 8 + n * C * 4 + dir_frac * 16 * n * C
     if kind == "blur":
         return blur_bytes_per_mvm(d, m, C, r, sym, False) / blur_launches(d, r)
-    if kind == "slice":      # CG variant: idx + w, U, out, and p
-        return n * D * 8 + chains * m * C * 4 + 2 * n * C * 4
-    if kind == "cg_update":  # q, r in; r out
-        return 3 * n * C * 4
+    if kind == "slice":      # CG variant: idx + w, U, p and r in, r out
+        return n * D * 8 + chains * m * C * 4 + 3 * n * C * 4
+    if kind == "cg_alpha":   # u and B u in
+        return 2 * m * C * 4
     if kind == "cg_dir":     # p, r, x in; p, x out
         return 5 * n * C * 4
     return 0.0
@@ -117,7 +118,7 @@ def sources_digest() -> dict:
 
 
 TRAFFIC_KERNELS = {"splat": ["k_splat_tile"], "splat_stage": ["k_splat_tile", "k_splat_gather", "k_gather_fix"],
-                   "blur": ["k_blur"], "slice": ["k_slice_tile"], "cg_update": ["k_cg_update"],
+                   "blur": ["k_blur"], "slice": ["k_slice_tile"], "cg_alpha": ["k_cg_alpha"],
                    "cg_dir": ["k_cg_dir"]}
 
 
@@ -518,8 +519,9 @@ def main(argv=None):
                 "operand_bytes_per_launch": native_b}
 
     names = {"splat": "k_splat_tile<double, G, true> (with the fused CG direction update)",
-             "blur": "k_blur2_split / k_blur2", "slice": "k_slice_tile<double, G, true>",
-             "cg_update": "k_cg_update", "cg_dir": "k_cg_dir"}
+             "blur": "k_blur2_split / k_blur2",
+             "slice": "k_slice_tile<double, G, true> (with the fused CG residual update)",
+             "cg_alpha": "k_cg_alpha", "cg_dir": "k_cg_dir"}
     single = {k: kernels[k]["total_ms"] for k in names if k in kernels}
     dom = max(single, key=single.get)
     splat_native = kernel_bytes("splat", n, d, m, C, 1, sym, cg=True, dir_frac=dir_frac)

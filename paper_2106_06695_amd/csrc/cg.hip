@@ -1,13 +1,16 @@
 // Conjugate gradients on (outputscale*K + noise*I) x = b, one independent
 // recurrence per column (Section 2, Krylov methods; Section 5.4 on
-// tolerances). All scalars stay on the device: the slice of each MVM emits
-// per-tile partial sums of p.q and its last block to finish turns them into
-// alpha; the update kernel moves r and emits partial sums of r.r, from which a
-// one-block kernel decides convergence and beta; the direction kernel moves x
-// and p. The
-// host only polls the per-column "active" flags every few iterations.
+// tolerances). All scalars stay on the device. Each iteration is one
+// lattice MVM that finishes the step itself: its splat applies the previous
+// direction update and emits p.p per tile; after the blur a lattice kernel
+// forms p.Ap = scale * u.(B u) + noise * p.p (u = W^T p: the quadratic
+// form of W B W^T taken on the m lattice rows instead of the n points) and
+// a one-block kernel turns it into alpha; the slice then moves the residual
+// (r -= alpha A p, never storing A p) and its last block decides
+// convergence and beta. The host only polls the per-column "active" flags
+// every few iterations.
 //
-// Precision: the recurrence vectors (r, p, q), the lattice values inside
+// Precision: the recurrence vectors (r, p), the lattice values inside
 // its MVMs and all reductions are fp64; the barycentric weights and x stay
 // fp32 (x is only accumulated, each update formed in fp64 and rounded once).
 // With an fp32 recurrence the recursive residual drifts from the true one by
@@ -34,13 +37,13 @@ namespace {
 // are solved together, so a column's iterates are the same alone or in a
 // batch. A block takes a superchunk at a time, kCpb(C) chunks per pass;
 // thread (chunk, group, column) has the column fastest, so the threads of a
-// group read whole rows. The update kernel, once per iteration, uses S = 16
-// (2048 rows), which keeps the scalar step's fold short; the init kernel
-// uses S = 1, which gives it more blocks for its gathered loads.
+// group read whole rows. The init kernel uses S = 1 over the points, which
+// gives it more blocks for its gathered loads; the alpha kernel S = 2 over
+// the lattice rows.
 constexpr int kCgChunk = 128;
 constexpr int kCgGroups = 16;
 constexpr int kCgRowsPerGroup = kCgChunk / kCgGroups;
-constexpr int kSuperUpdate = 16;
+constexpr int kSuperLat = 2;
 constexpr int kSuperInit = 1;
 __host__ __device__ inline int64_t cg_chunks(int64_t n) { return (n + kCgChunk - 1) / kCgChunk; }
 __host__ __device__ inline int64_t cg_supers(int64_t n, int S) { return (cg_chunks(n) + S - 1) / S; }
@@ -115,51 +118,42 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
   });
 }
 
-// r -= alpha q, and r.r (x and p move in the next splat, which reads p
-// anyway, or in k_cg_dir).
-__global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ r,
-                                                      const double* __restrict__ q_, int64_t n, int C,
-                                                      const CgState* __restrict__ st,
-                                                      double* __restrict__ partials) {
+// Partial sums of p.Ap for alpha. Blocks [0, lat_parts) take one
+// superchunk of lattice rows each: scale * u.(B u) per column (the
+// quadratic form p.(scale K) p). Block lat_parts + g adds tile rows
+// 16g .. 16g + 15 of the splat's noise * p.p in order. k_cg_scalar then
+// folds all of these rows into p.Ap and alpha (the order depends on m and
+// the tile count only); a last-block fold here would cost every one of the
+// thousands of blocks a device-scope fence.
+__global__ __launch_bounds__(kBlock) void k_cg_alpha(const double* __restrict__ u,
+                                                     const double* __restrict__ bu, int64_t m, int C,
+                                                     double scale, int64_t lat_parts,
+                                                     const double* __restrict__ pp, int64_t ntiles,
+                                                     CgHook h) {
   extern __shared__ double dsh[];
-  cg_partials<kSuperUpdate>(n, C, partials, dsh, [=](int64_t i0, int c) {
-    const double a = st->alpha[c];
-    // all loads of the group first, then the stores; a whole group (every
-    // group but possibly the last) has no per-row branches, which would make
-    // each store wait for the one before it
-    double qv[kCgRowsPerGroup], rv[kCgRowsPerGroup];
+  cg_partials<kSuperLat>(m, C, h.partials, dsh, [=](int64_t i0, int c) {
+    double uv[kCgRowsPerGroup], bv[kCgRowsPerGroup];
+#pragma unroll
+    for (int k = 0; k < kCgRowsPerGroup; ++k) {
+      const int64_t e = (i0 + k < m ? i0 + k : m - 1) * C + c;
+      uv[k] = u[e];
+      bv[k] = bu[e];
+    }
     double dot = 0.0;
-    if (i0 + kCgRowsPerGroup <= n) {
 #pragma unroll
-      for (int k = 0; k < kCgRowsPerGroup; ++k) {
-        const int64_t e = (i0 + k) * C + c;
-        qv[k] = q_[e];
-        rv[k] = r[e];
-      }
-#pragma unroll
-      for (int k = 0; k < kCgRowsPerGroup; ++k) {
-        const double v = __builtin_fma(-a, qv[k], rv[k]);
-        r[(i0 + k) * C + c] = v;
-        dot += v * v;
-      }
-      return dot;
-    }
-#pragma unroll
-    for (int k = 0; k < kCgRowsPerGroup; ++k) {
-      const int64_t e = (i0 + k) * C + c;
-      qv[k] = i0 + k < n ? q_[e] : 0.0;
-      rv[k] = i0 + k < n ? r[e] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < kCgRowsPerGroup; ++k) {
-      if (i0 + k < n) {
-        const double v = __builtin_fma(-a, qv[k], rv[k]);
-        r[(i0 + k) * C + c] = v;
-        dot += v * v;
-      }
-    }
-    return dot;
+    for (int k = 0; k < kCgRowsPerGroup; ++k)
+      if (i0 + k < m) dot = __builtin_fma(uv[k], bv[k], dot);
+    return scale * dot;
   });
+  const int64_t g = (int64_t)blockIdx.x - lat_parts;
+  if (g >= 0) {
+    const int64_t t0 = g * 16, t1 = t0 + 16 < ntiles ? t0 + 16 : ntiles;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+      double v = 0.0;
+      for (int64_t t = t0; t < t1; ++t) v += pp[t * C + c];
+      h.partials[(lat_parts + g) * C + c] = v;
+    }
+  }
 }
 
 // The scalar step after a vector kernel, in one block of its own: the
@@ -212,6 +206,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(float* __restrict__ x, const 
 }
 
 }  // namespace
+
+int launch_cg_alpha(const double* u, const double* bu, int64_t m, int C, double scale, const CgMvm& cg,
+                    hipStream_t s) {
+  const int64_t groups = (cg.ntiles + 15) / 16;
+  {
+    ProfScope ps(KK_CG_ALPHA, s);
+    hipLaunchKernelGGL(k_cg_alpha, dim3((unsigned)(cg.lat_parts + groups)), dim3(kBlock), cg_vec_lds(C), s, u, bu,
+                       m, C, scale, cg.lat_parts, (const double*)cg.pp, cg.ntiles, cg.alpha);
+    SGP_LAUNCH_CHECK("k_cg_alpha");
+  }
+  {
+    ProfScope ps(KK_CG_SCALAR, s);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, cg.alpha, C);
+    SGP_LAUNCH_CHECK("k_cg_scalar");
+  }
+  return SGP_OK;
+}
 
 int launch_cg_dir(const CgDirUpdate& up, int64_t nC, int C, hipStream_t s) {
   ProfScope ps(KK_CG_DIR, s);
@@ -285,24 +296,30 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
   sgp_lattice* Lm = const_cast<sgp_lattice*>(L);
   const int64_t n = L->n, nC = n * C;
   int rc;
-  // r, p, q in fp64, then x in fp32
-  if ((rc = dev_reserve(L, Lm->cgvec, (sizeof(double) * 3 + sizeof(float)) * nC, s))) return rc;
-  // partial sums: one row per superchunk from the vector kernels, one row
-  // per tile from the slice; then the scalar state, and the finished-block
-  // counter of the slice's last-block fold
-  const int64_t iparts = cg_supers(n, kSuperInit), uparts = cg_supers(n, kSuperUpdate);
-  const int64_t nparts = std::max(L->ntiles, iparts);
-  const size_t part_bytes = ((sizeof(double) * nparts * C + 255) / 256) * 256;
+  // r, p in fp64, then x in fp32
+  if ((rc = dev_reserve(L, Lm->cgvec, (sizeof(double) * 2 + sizeof(float)) * nC, s))) return rc;
+  // partial sums: one row per superchunk from the init kernel or per tile
+  // from the slice (r.r); one per superchunk of lattice rows and per 16
+  // tiles (alpha); one per tile from the splat (p.p); then the scalar
+  // state, and the finished-block counter of the last-block folds
+  const int64_t iparts = cg_supers(n, kSuperInit);
+  const int64_t lparts = cg_supers(L->m, kSuperLat), groups = (L->ntiles + 15) / 16;
+  const int64_t rparts = std::max(L->ntiles, iparts);
+  auto rows_bytes = [&](int64_t rows) { return ((sizeof(double) * rows * C + 255) / 256) * 256; };
+  const size_t rr_bytes = rows_bytes(rparts), al_bytes = rows_bytes(lparts + groups);
+  const size_t pp_bytes = rows_bytes(L->ntiles);
   const size_t st_bytes = ((sizeof(CgState) + 255) / 256) * 256;
-  const size_t red_bytes = part_bytes + st_bytes + 256;
+  const size_t red_bytes = rr_bytes + al_bytes + pp_bytes + st_bytes + 256;
   if ((rc = dev_reserve(L, Lm->cgred, red_bytes, s))) return rc;
   double* r = (double*)Lm->cgvec.ptr;
   double* p = r + nC;
-  double* q = p + nC;
-  float* x32 = (float*)(q + nC);
-  double* partials = (double*)Lm->cgred.ptr;
-  CgState* st = (CgState*)((char*)Lm->cgred.ptr + part_bytes);
-  unsigned* counter = (unsigned*)((char*)Lm->cgred.ptr + part_bytes + st_bytes);
+  float* x32 = (float*)(p + nC);
+  char* red = (char*)Lm->cgred.ptr;
+  double* rr_parts = (double*)red;
+  double* al_parts = (double*)(red + rr_bytes);
+  double* pp_parts = (double*)(red + rr_bytes + al_bytes);
+  CgState* st = (CgState*)(red + rr_bytes + al_bytes + pp_bytes);
+  unsigned* counter = (unsigned*)(red + rr_bytes + al_bytes + pp_bytes + st_bytes);
 
   int32_t* host = (int32_t*)pinned_scratch(sizeof(int32_t) * 3 * kMaxCgCols);
   if (!host) {
@@ -312,16 +329,20 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
 
   const dim3 block(kBlock);
   const dim3 igrid((unsigned)std::min<int64_t>(iparts, 65536));
-  const dim3 ugrid((unsigned)std::min<int64_t>(uparts, 65536));
   const size_t vlds = cg_vec_lds(C);
-  const CgHook h_start{partials, iparts, st, counter, (int)SM_START, (double)tol};
-  const CgHook h_alpha{partials, L->ntiles, st, counter, (int)SM_ALPHA, (double)tol};
-  const CgHook h_beta{partials, uparts, st, counter, (int)SM_BETA, (double)tol};
+  const CgHook h_start{rr_parts, iparts, st, counter, (int)SM_START, (double)tol};
+  CgMvm cgm;
+  cgm.alpha = CgHook{al_parts, lparts + groups, st, counter, (int)SM_ALPHA, (double)tol};
+  cgm.lat_parts = lparts;
+  cgm.pp = pp_parts;
+  cgm.ntiles = L->ntiles;
+  cgm.beta = CgHook{rr_parts, L->ntiles, st, counter, (int)SM_BETA, (double)tol};
+  cgm.r = r;
   if ((rc = launch_fill_u32(counter, 1, 0u, s))) return rc;
   {
     ProfScope ps(KK_CG_INIT, s);
     hipLaunchKernelGGL(k_cg_init, igrid, block, vlds, s, b, (const uint32_t*)L->perm.ptr, x32, r, p, n, C,
-                       L->solve_rows, partials);
+                       L->solve_rows, rr_parts);
     SGP_LAUNCH_CHECK("k_cg_init");
   }
   {
@@ -329,27 +350,18 @@ int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, in
     hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, h_start, C);
     SGP_LAUNCH_CHECK("k_cg_scalar");
   }
-  // One iteration: q = A p (the slice's last block turns p.q into alpha),
-  // r and its norm, convergence and beta, then x and p. Nothing here talks to the host, so a block of iterations
-  // can be recorded as a graph.
+  // One iteration: one MVM of p that also yields alpha, r -= alpha A p,
+  // convergence and beta (CgMvm); x and p move in the next iteration's
+  // splat. Nothing here talks to the host, so a block of iterations can be
+  // recorded as a graph.
   // The direction update x += alpha p, p = r + beta p of an iteration runs
   // in the next iteration's splat (CgDirUpdate), or as a pass of its own
   // when that fusion is switched off; both give the same values bit for bit.
   const bool fused = cg_fuse_enabled();
   const CgDirUpdate dirup{p, r, x32, st};
   auto iterate = [&](hipStream_t st_, bool first) -> int {
-    int rc_ = mvm_cg(L, p, C, q, st_, (double)noise, &h_alpha, (fused && !first) ? &dirup : nullptr);
+    int rc_ = mvm_cg(L, p, C, st_, (double)noise, cgm, (fused && !first) ? &dirup : nullptr);
     if (rc_) return rc_;
-    {
-      ProfScope ps(KK_CG_UPDATE, st_);
-      hipLaunchKernelGGL(k_cg_update, ugrid, block, vlds, st_, r, q, n, C, (const CgState*)st, partials);
-      SGP_LAUNCH_CHECK("k_cg_update");
-    }
-    {
-      ProfScope ps(KK_CG_SCALAR, st_);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st_, h_beta, C);
-      SGP_LAUNCH_CHECK("k_cg_scalar");
-    }
     if (!fused) {
       const int rc2 = launch_cg_dir(dirup, nC, C, st_);
       if (rc2) return rc2;

@@ -42,6 +42,25 @@ struct CgHook {
   double tol;
 };
 
+// What the MVM of a CG iteration does besides A p. Its alpha needs p.Ap,
+// which equals scale * u.(B u) + noise * p.p for the splatted u = W^T p and
+// the blurred B u (the quadratic form of W B W^T taken on the lattice), so
+// it is known before the slice, and the slice moves r itself.
+//   pp:    row t gets noise * p.p of tile t (from the splat).
+//   alpha: rows [0, lat_parts) of its partials get scale * u.Bu of a
+//          block of lattice rows, the rows after them the sums of 16
+//          consecutive pp rows; a one-block launch folds them into alpha.
+//   beta:  row t of its partials gets the new r.r of tile t (from the
+//          slice, which updates r in place); its last block folds beta.
+struct CgMvm {
+  CgHook alpha;
+  int64_t lat_parts;
+  double* pp;
+  int64_t ntiles;
+  CgHook beta;
+  double* r;
+};
+
 constexpr int kFold = 64;  // fixed fold width: the order depends on nparts only
 
 // Sum the nparts partial rows of each column in a fixed order and apply one

@@ -345,7 +345,7 @@ int64_t g_prof_launches[KK_NUM] = {};
 double g_prof_ms[KK_NUM] = {};
 const char* const kKindNames[KK_NUM] = {
     "fill", "simplex_insert", "count_first", "scan", "compact", "resolve", "neighbors",
-    "splat", "splat_gather", "blur", "slice", "cg_init", "cg_scalar", "cg_update", "cg_dir", "cg_out", "grad", "sort", "order"};
+    "splat", "splat_gather", "blur", "slice", "cg_init", "cg_scalar", "cg_dir", "cg_alpha", "cg_out", "grad", "sort", "order"};
 
 // Fold completed records into the totals. Caller holds the mutex.
 int prof_drain() {

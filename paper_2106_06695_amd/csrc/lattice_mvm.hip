@@ -195,6 +195,7 @@ struct SplatArgs {
   int P, D, C, chunks;
   int vec_v;  // V rows of a tile are one contiguous run of 16-byte vectors
   int cvec;   // rows of C channels start 16-byte aligned
+  double pp_scale;  // CG: factor of each tile's p . p (the noise variance)
   SplatLds lds;
 };
 
@@ -214,12 +215,14 @@ struct SplatArgs {
 // is what the tile splats.
 // DIR: the fused variant; it is launched only where the tile's values are
 // whole 16-byte vectors of C == G columns in internal order (vec_v).
+// pp (CG, else null): row t receives pp_scale * p.p of tile t per column,
+// from the staged values.
 template <typename TU, int G, bool DIR>
 __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_splat_tile(
     const int32_t* __restrict__ tile_off, const uint16_t* __restrict__ run_rel,
     const int32_t* __restrict__ run_dst, const uint8_t* __restrict__ ent_lp,
     const float* __restrict__ ent_w, const TU* __restrict__ V, const uint32_t* __restrict__ perm,
-    TU* __restrict__ part, SplatArgs<TU> a, CgDirUpdate up) {
+    TU* __restrict__ part, double* __restrict__ pp, SplatArgs<TU> a, CgDirUpdate up) {
   using S = TileShape<TU, G, kSplatBlock>;
   extern __shared__ __align__(16) unsigned char smem[];
   // CG: alpha, beta and the active flags of the columns, for the update
@@ -382,6 +385,33 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
     }
     __syncthreads();
     if (item + step < end) fetch(item + step);  // in flight while this tile is reduced
+
+    if constexpr (sizeof(TU) == 8) {
+      if (pp) {
+        // CG: the tile's p . p per column from the staged values, its points
+        // in 16 blocks of 16, each block and then the blocks added in index
+        // order, so that the sum does not depend on the channel chunk; the
+        // 16 lanes of a column are consecutive (one wave)
+        const int64_t tt = item / a.chunks;
+        const int cc0 = (int)(item % a.chunks) * G;
+        const int np = cur_ne / a.D;
+        for (int pr = tid; pr < 16 * G; pr += kSplatBlock) {
+          const int c = pr / 16, blk = pr % 16;
+          double v = 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int q = blk * 16 + u;
+            const double x = q < np ? (double)lv[q * S::RS + c] : 0.0;
+            v = __builtin_fma(x, x, v);
+          }
+          double tot = 0.0;
+          const int l0 = (tid & 63) & ~15;
+#pragma unroll
+          for (int b = 0; b < 16; ++b) tot += __shfl(v, l0 + b);
+          if (blk == 0 && cc0 + c < a.C) pp[tt * a.C + cc0 + c] = a.pp_scale * tot;
+        }
+      }
+    }
 
     const int ch = (int)(item % a.chunks);
     const int grp = tid / S::LPR;
@@ -862,13 +892,15 @@ struct SliceArgs {
 // out = scale * W U restricted to one tile (Section 3.2, Slice). The tile's
 // (slot, weight) entries and its first RC lattice rows arrive in registers
 // while the previous tile is computed; a tile with more runs stages the rest
-// RC rows at a time. Each point is combined by LPR lanes of
-// VW channels from the staged rows. The CG variant adds noise * p and emits
-// the tile's p . out per column, reduced in a fixed order.
+// RC rows at a time. Each point is combined by LPR lanes of VW channels from
+// the staged rows. The CG variant forms q = out + noise * p, moves the
+// residual (out is r: r -= alpha q, alpha already known) and emits the
+// tile's new r . r per column, reduced in a fixed order.
 template <typename TU, int G, bool CG>
 // perm: caller row of each sorted point, or null. CG only: p is the
-// direction (sorted order), partials receive each tile's p . out per
-// column, mperm maps sorted points to caller rows for the mrows mask.
+// direction and out the residual (sorted order), hook.partials receive each
+// tile's r . r per column, mperm maps sorted points to caller rows for the
+// mrows mask.
 __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
     const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_verts,
     const uint16_t* __restrict__ loc, const float* __restrict__ ws, const TU* __restrict__ U,
@@ -945,6 +977,11 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
     }
   };
 
+  // CG: alpha of every column (known before this kernel)
+  __shared__ TU s_alpha[CG ? kMaxCgCols : 1];
+  if constexpr (CG) {
+    for (int c = tid; c < a.C && c < kMaxCgCols; c += kSliceBlock) s_alpha[c] = (TU)hook.st->alpha[c];
+  }
   int64_t item, end, step;
   xcd_items(a.items, &item, &end, &step);
   for (int i = tid; i < S::RS; i += kSliceBlock) lu[a.lds.zrow * S::RS + i] = (TU)0;  // the zero row
@@ -974,26 +1011,35 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
     const int cg = ch * G + cl;
     const bool live = cg < a.C;
     const bool full = cg + S::VW <= a.C;
-    // CG: this thread's p values, requested before the next tile's loads
-    // so that using them never waits for those
-    TU pv[S::PPG][S::VW];
+    // CG: this thread's p and r values, requested before the next tile's
+    // loads so that using them never waits for those
+    TU pv[S::PPG][S::VW], rv[S::PPG][S::VW];
 #pragma unroll
     for (int k = 0; k < S::PPG; ++k) {
       const int lp = grp + k * S::NG;
 #pragma unroll
-      for (int i = 0; i < S::VW; ++i) pv[k][i] = 0;
+      for (int i = 0; i < S::VW; ++i) {
+        pv[k][i] = 0;
+        rv[k][i] = 0;
+      }
       if (CG && lp < cur_np && live) {
         const int64_t pt = t * a.P + lp;
         const TU* src = p + pt * a.C + cg;
+        const TU* rsrc = out + pt * a.C + cg;
         if (full && a.cvec) {
           read_row<TU, S::VW>(src, pv[k]);
+          read_row<TU, S::VW>(rsrc, rv[k]);
         } else {
 #pragma unroll
           for (int i = 0; i < S::VW; ++i)
-            if (cg + i < a.C) pv[k][i] = src[i];
+            if (cg + i < a.C) {
+              pv[k][i] = src[i];
+              rv[k][i] = rsrc[i];
+            }
         }
       }
     }
+
     const bool next = item + step < end;
     if (next) fetch_index(item + step);
     TU acc[S::PPG][S::VW];
@@ -1048,7 +1094,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
         }
       }
     }
-    double prod[S::PPG][S::VW];  // CG: p . out of each (point, channel)
+    double prod[S::PPG][S::VW];  // CG: r . r of each (point, channel)
 #pragma unroll
     for (int k = 0; k < S::PPG; ++k) {
       const int lp = grp + k * S::NG;
@@ -1062,8 +1108,9 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
         for (int i = 0; i < S::VW; ++i) {
           o[i] = a.scale * acc[k][i];
           if (CG) {
-            o[i] = masked ? (TU)0 : fma_t(a.noise, pv[k][i], o[i]);
-            prod[k][i] = (double)pv[k][i] * (double)o[i];
+            const TU q = masked ? (TU)0 : fma_t(a.noise, pv[k][i], o[i]);
+            o[i] = fma_t(-s_alpha[cg + i < a.C ? cg + i : 0], q, rv[k][i]);
+            prod[k][i] = (double)o[i] * (double)o[i];
           }
         }
         TU* dstp = out + (perm ? (int64_t)perm[pt] : pt) * a.C + cg;
@@ -1077,7 +1124,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
       }
     }
     if (CG) {
-      // the tile's p . out per column: points in 16 blocks of 16, each block
+      // the tile's r . r per column: points in 16 blocks of 16, each block
       // and then the blocks added in index order, so that the sum does not
       // depend on how channels are split over lanes; 16 channels per pass
       double* sh = (double*)smem;            // [256 points][16 channels]
@@ -1095,9 +1142,16 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
         }
         __syncthreads();
         if (tid < 256) {
+          // every row is read (rows past the tile hold stale values and add
+          // nothing), so the reads need no branches
           const int c16 = tid % 16, blk = tid / 16;
+          const double* src = sh + blk * 256 + c16;
+          double x[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) x[u] = src[u * 16];
           double v = 0.0;
-          for (int q = blk * 16; q < blk * 16 + 16; ++q) v += q < cur_np ? sh[q * 16 + c16] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) v += blk * 16 + u < cur_np ? x[u] : 0.0;
           sh2[blk * 16 + c16] = v;
         }
         __syncthreads();
@@ -1109,7 +1163,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
       }
     }
   }
-  // CG: the last block to finish folds the tiles' p . q into alpha
+  // CG: the last block to finish folds the tiles' r . r into beta
   if constexpr (CG) cg_finish(hook, a.C, (double*)smem);
 }
 
@@ -1218,23 +1272,27 @@ void split_rows(int64_t rows, int R, int64_t cap, unsigned* blocks, int64_t* row
 }
 
 // Work memory of one MVM in elements of its accumulator type: four m x C
-// lattice value arrays (the splat's result and the blur's ping-pong), one
+// lattice value arrays (the splat's result and the blur's ping-pong; a
+// fifth inside CG, where the splat's result must outlive the blur), one
 // partial row per run piece, two fragment rows per gather range.
-size_t mvm_work_elems(const sgp_lattice* L, int C) {
-  return (size_t)(4 * L->m + L->npiece + 2 * gather_ranges(L)) * (size_t)C;
+size_t mvm_work_elems(const sgp_lattice* L, int C, bool cg) {
+  return (size_t)((cg ? 5 : 4) * L->m + L->npiece + 2 * gather_ranges(L)) * (size_t)C;
 }
 
+// cgm (CG only, else null): V is the direction p, out the residual r (both
+// internal order), and the MVM finishes the CG step (CgMvm).
 template <typename TU, int G>
 int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out, hipStream_t s,
-          TU noise, const TU* p, const CgHook* hook, const LaunchChoice& lc, void* work,
-          const CgDirUpdate* up) {
+          TU noise, const CgMvm* cgm, const LaunchChoice& lc, void* work, const CgDirUpdate* up) {
   const int d = L->d, D = d + 1, T = 2 * L->order;
   const int64_t m = L->m, mC = m * C;
+  const TU* p = cgm ? V : nullptr;
   TU* U0 = (TU*)work;
   TU* B1 = U0 + mC;
   TU* B2 = B1 + mC;
   TU* B3 = B2 + mC;
-  TU* part = B3 + mC;
+  TU* B4 = cgm ? B3 + mC : U0;  // chain 1's second array (U0 itself outside CG)
+  TU* part = (cgm ? B4 : B3) + mC;
   TU* frag = part + L->npiece * C;  // 2 rows per gather range
   const int chunks = (C + G - 1) / G;
   const int P = L->tile_points;
@@ -1250,6 +1308,8 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   sa.vec_v = (TileShape<TU, G, kSplatBlock>::VEC && !perm && C == G && aligned16(V)) ? 1 : 0;
   sa.cvec = (C % Vec16<TU>::N == 0 && aligned16(part)) ? 1 : 0;
   sa.lds = splat_lds<TU>(P, D, L->max_tile_pieces, G);
+  sa.pp_scale = cgm ? (double)noise : 0.0;
+  double* pp = cgm ? cgm->pp : nullptr;
   // the previous CG iteration's direction update: in this splat where its
   // values are whole vectors of all C columns, else as a pass of its own
   const bool dir_fused = up && sizeof(TU) == 8 && TileShape<TU, G, kSplatBlock>::VEC && sa.vec_v;
@@ -1266,12 +1326,12 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
       hipLaunchKernelGGL((k_splat_tile<TU, G, true>), dim3(grid), dim3(kSplatBlock), sa.lds.total, s,
                          (const int32_t*)L->stile_off.ptr, (const uint16_t*)L->run_rel.ptr,
                          (const int32_t*)L->run_dst.ptr, (const uint8_t*)L->ent_lp.ptr,
-                         (const float*)L->ent_w.ptr, V, perm, part, sa, *up);
+                         (const float*)L->ent_w.ptr, V, perm, part, pp, sa, *up);
     else
       hipLaunchKernelGGL((k_splat_tile<TU, G, false>), dim3(grid), dim3(kSplatBlock), sa.lds.total, s,
                          (const int32_t*)L->stile_off.ptr, (const uint16_t*)L->run_rel.ptr,
                          (const int32_t*)L->run_dst.ptr, (const uint8_t*)L->ent_lp.ptr,
-                         (const float*)L->ent_w.ptr, V, perm, part, sa, CgDirUpdate{});
+                         (const float*)L->ent_w.ptr, V, perm, part, pp, sa, CgDirUpdate{});
     SGP_LAUNCH_CHECK("k_splat_tile");
   }
   {
@@ -1309,11 +1369,11 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   a.nt = (4.0 * (double)mC * sizeof(TU) > 256.0 * (1 << 20)) ? 1 : 0;
   const int32_t* nbr = (const int32_t*)L->nbr.ptr;
   // Chain 0 moves between B1 and B3 and never writes U0, which chain 1 reads
-  // first; chain 1 moves between B2 and U0. Steps run in fused pairs when
-  // the stencil has three taps.
+  // first; chain 1 moves between B2 and B4 (U0 outside CG). Steps run in
+  // fused pairs when the stencil has three taps.
   const TU* cur[2] = {U0, U0};
   auto next0 = [&](const TU* c0) { return c0 == B1 ? B3 : B1; };
-  auto next1 = [&](const TU* c1) { return c1 == B2 ? U0 : B2; };
+  auto next1 = [&](const TU* c1) { return c1 == B2 ? B4 : B2; };
   auto kdir = [&](int step, int chain) {
     return chain == 0 ? ((L->blur == SGP_BLUR_REVERSE) ? d - step : step) : d - step;
   };
@@ -1368,6 +1428,11 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
     cur[1] = dst1;
   }
   const TU scale = sym ? (TU)(0.5 * (double)L->outputscale) : (TU)L->outputscale;
+  if (cgm) {
+    // alpha from p.Ap = scale * u.(B u) + noise * p.p, before the slice
+    const int rc = launch_cg_alpha((const double*)U0, (const double*)cur[0], m, C, (double)scale, *cgm, s);
+    if (rc) return rc;
+  }
   ProfScope ps(KK_SLICE, s);
   SliceArgs<TU> la;
   la.n = L->n;
@@ -1379,18 +1444,18 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   la.cvec = (C % Vec16<TU>::N == 0 && aligned16(out) && (!p || aligned16(p))) ? 1 : 0;
   la.scale = scale;
   la.noise = noise;
-  la.mrows = hook ? L->solve_rows : 0;
+  la.mrows = cgm ? L->solve_rows : 0;
   la.lds = slice_lds<TU, G>(P, D, maxq);
   const int32_t* toff = (const int32_t*)L->tile_off.ptr;
   const int32_t* tverts = (const int32_t*)L->tile_verts.ptr;
   const uint16_t* loc = (const uint16_t*)L->loc.ptr;
   const float* ws = (const float*)L->ws.ptr;
   const uint32_t* mperm = (const uint32_t*)L->perm.ptr;
-  if (hook) {
+  if (cgm) {
     const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, true>, kSliceBlock, la.lds.total,
                                           la.items, lc.slice_bpc);
     hipLaunchKernelGGL((k_slice_tile<TU, G, true>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
-                       tverts, loc, ws, (const TU*)cur[0], out, perm, p, *hook, mperm, la);
+                       tverts, loc, ws, (const TU*)cur[0], out, perm, p, cgm->beta, mperm, la);
   } else {
     const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, false>, kSliceBlock, la.lds.total,
                                           la.items, lc.slice_bpc);
@@ -1418,14 +1483,15 @@ int chunk_lanes(const sgp_lattice* L, int C, size_t elem) {
   return g;
 }
 
-// work: the MVM's work memory (mvm_work_elems(L, C) elements of TU), or
-// null for the lattice's own buffer, grown on demand.
+// work: the MVM's work memory (mvm_work_elems(L, C, cgm) elements of TU),
+// or null for the lattice's own buffer, grown on demand.
 template <typename TU>
 int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* out,
-                 hipStream_t s, TU noise, const TU* p, const CgHook* hook, void* work = nullptr,
+                 hipStream_t s, TU noise, const CgMvm* cgm, void* work = nullptr,
                  const CgDirUpdate* up = nullptr) {
   if (!work) {
-    int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf, sizeof(TU) * mvm_work_elems(L, C), s);
+    int rc = dev_reserve(L, const_cast<sgp_lattice*>(L)->ubuf,
+                         sizeof(TU) * mvm_work_elems(L, C, cgm != nullptr), s);
     if (rc) return rc;
     work = L->ubuf.ptr;
   }
@@ -1437,30 +1503,29 @@ int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C,
     (void)tune_find(L, C, (int)sizeof(TU), &lc);
   if (lc.g < 1 || lc.g > gmax || (lc.g & (lc.g - 1))) lc.g = gmax;  // never wider than the LDS allows
   switch (lc.g) {
-    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
-    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
-    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
-    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
-    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
-    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
-    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, p, hook, lc, work, up);
+    case 1: return mvm_g<TU, 1>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
+    case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
+    case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
+    case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
+    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
+    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
+    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
   }
 }
 
 }  // namespace
 
 int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s) {
-  return mvm_dispatch<float>(L, V, (const uint32_t*)L->perm.ptr, C, out, s, 0.f, nullptr,
-                                    nullptr);
+  return mvm_dispatch<float>(L, V, (const uint32_t*)L->perm.ptr, C, out, s, 0.f, nullptr);
 }
 
-int mvm_cg(const sgp_lattice* L, double* p, int C, double* q, hipStream_t s, double noise,
-           const CgHook* hook, const CgDirUpdate* up) {
-  return mvm_dispatch<double>(L, p, nullptr, C, q, s, noise, p, hook, nullptr, up);
+int mvm_cg(const sgp_lattice* L, double* p, int C, hipStream_t s, double noise, const CgMvm& cg,
+           const CgDirUpdate* up) {
+  return mvm_dispatch<double>(L, p, nullptr, C, cg.r, s, noise, &cg, nullptr, up);
 }
 
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s) {
-  return mvm_dispatch<double>(L, V, nullptr, C, out, s, 0.0, nullptr, nullptr);
+  return mvm_dispatch<double>(L, V, nullptr, C, out, s, 0.0, nullptr);
 }
 
 // Times every candidate launch choice on this lattice and keeps the fastest
@@ -1618,7 +1683,7 @@ extern "C" int lattice_mvm_noalloc(const sgp_lattice* L, const float* values, in
     set_error("lattice_mvm_noalloc: out overlaps values");
     return SGP_EINVAL;
   }
-  const size_t need = sizeof(float) * mvm_work_elems(L, C);
+  const size_t need = sizeof(float) * mvm_work_elems(L, C, false);
   if (need > kScratchBytes) {
     set_error("lattice_mvm_noalloc: this lattice and C = %d need %zu bytes of work memory; the "
               "no-allocation entry point has %zu (use lattice_mvm)", (int)C, need, kScratchBytes);
@@ -1634,7 +1699,7 @@ extern "C" int lattice_mvm_noalloc(const sgp_lattice* L, const float* values, in
   int rc = scratch_address(dev, &work);
   if (rc) return rc;
   rc = mvm_dispatch<float>(L, values, (const uint32_t*)L->perm.ptr, C, out, (hipStream_t)stream, 0.f,
-                           nullptr, nullptr, work);
+                           nullptr, work);
   if (rc == SGP_OK) mark_use(L, (hipStream_t)stream);
   return rc;
 }

@@ -58,8 +58,8 @@ enum KernelKind {
   KK_SLICE,
   KK_CG_INIT,
   KK_CG_SCALAR,
-  KK_CG_UPDATE,
   KK_CG_DIR,
+  KK_CG_ALPHA,
   KK_CG_OUT,
   KK_GRAD,
   KK_SORT,
@@ -216,15 +216,19 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, i
 void build_tune_reset();
 // fp32 values, fp32 lattice accumulation (lattice_mvm)
 int mvm_into(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s);
-// fp64 values and accumulation with the CG epilogue: q = A p, partial sums
-// of p.q; up (may be null) is the previous iteration's direction update,
-// which the splat applies to p (in place) and x before splatting p
-struct CgHook;
+// fp64 values and accumulation inside CG: A p, then alpha, r -= alpha A p
+// and beta (CgMvm); up (may be null) is the previous iteration's direction
+// update, which the splat applies to p (in place) and x before splatting p
+struct CgMvm;
 struct CgDirUpdate;
 // The CG direction update as a pass of its own over the n x C arrays
 int launch_cg_dir(const CgDirUpdate& up, int64_t nC, int C, hipStream_t s);
-int mvm_cg(const sgp_lattice* L, double* p, int C, double* q, hipStream_t s, double noise,
-           const CgHook* hook, const CgDirUpdate* up);
+// alpha of a CG step from the splatted u, the blurred B u (m x C each) and
+// the splat's p.p tile rows
+int launch_cg_alpha(const double* u, const double* bu, int64_t m, int C, double scale, const CgMvm& cg,
+                    hipStream_t s);
+int mvm_cg(const sgp_lattice* L, double* p, int C, hipStream_t s, double noise, const CgMvm& cg,
+           const CgDirUpdate* up);
 // fp64 values and accumulation, internal point order, no epilogue
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s);
 }  // namespace sgp

@@ -81,11 +81,11 @@ def build_peak_bytes(N: int, d: int, order: int = 1) -> int:
 
 
 def solve_bytes(N: int, C: int, d: int, m: int) -> int:
-    """Solver and MVM work buffers: fp64 lattice values (4 m rows plus at
-    most N(d+1) tile-run rows), three fp64 CG vectors and an fp32 one, and
+    """Solver and MVM work buffers: fp64 lattice values (5 m rows plus at
+    most N(d+1) tile-run rows), two fp64 CG vectors and an fp32 one, and
     the request's own fp32 inputs and outputs."""
     runs = N * (d + 1)
-    return int(8 * C * (4 * m + runs) + 28 * N * C + 4 * N * (d + 2 * C + 2) + (16 << 20))
+    return int(8 * C * (5 * m + runs) + 20 * N * C + 4 * N * (d + 2 * C + 2) + (16 << 20))
 
 
 def footprint_worst(req) -> int:

@@ -100,7 +100,7 @@ def test_mvm_and_cg_argument_errors(lib):
 def test_profiler_kinds(lib):
     kinds = lib.sgp_profile_kinds()
     names = [lib.sgp_profile_name(k).decode() for k in range(kinds)]
-    for needed in ("splat", "blur", "slice", "simplex_insert", "cg_update"):
+    for needed in ("splat", "blur", "slice", "simplex_insert", "cg_alpha"):
         assert needed in names
     assert lib.sgp_profile_read(kinds, None, None) == -1
     launches, ms = ctypes.c_int64(), ctypes.c_double()
