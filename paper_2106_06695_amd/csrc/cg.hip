@@ -121,15 +121,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const float* __restrict__ b,
 // Partial sums of p.Ap for alpha. Blocks [0, lat_parts) take one
 // superchunk of lattice rows each: scale * u.(B u) per column (the
 // quadratic form p.(scale K) p). Block lat_parts + g adds tile rows
-// 16g .. 16g + 15 of the splat's noise * p.p in order. k_cg_scalar then
-// folds all of these rows into p.Ap and alpha (the order depends on m and
-// the tile count only); a last-block fold here would cost every one of the
-// thousands of blocks a device-scope fence.
+// 16g .. 16g + 15 of the splat's noise * p.p in order. All of these rows
+// are then folded into p.Ap and alpha (the order depends on m and the tile
+// count only): by the last block to finish when the kernel has few blocks
+// (fold), else by k_cg_scalar, as a device-scope fence in every one of
+// thousands of blocks costs more than the launch.
+constexpr int64_t kAlphaFoldBlocks = 256;
 __global__ __launch_bounds__(kBlock) void k_cg_alpha(const double* __restrict__ u,
                                                      const double* __restrict__ bu, int64_t m, int C,
                                                      double scale, int64_t lat_parts,
                                                      const double* __restrict__ pp, int64_t ntiles,
-                                                     CgHook h) {
+                                                     CgHook h, int fold) {
   extern __shared__ double dsh[];
   cg_partials<kSuperLat>(m, C, h.partials, dsh, [=](int64_t i0, int c) {
     double uv[kCgRowsPerGroup], bv[kCgRowsPerGroup];
@@ -154,6 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_alpha(const double* __restrict__ 
       h.partials[(lat_parts + g) * C + c] = v;
     }
   }
+  if (fold) cg_finish(h, C, dsh);
 }
 
 // The scalar step after a vector kernel, in one block of its own: the
@@ -209,14 +212,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(float* __restrict__ x, const 
 
 int launch_cg_alpha(const double* u, const double* bu, int64_t m, int C, double scale, const CgMvm& cg,
                     hipStream_t s) {
-  const int64_t groups = (cg.ntiles + 15) / 16;
+  const int64_t blocks = cg.lat_parts + (cg.ntiles + 15) / 16;
+  const int fold = blocks <= kAlphaFoldBlocks ? 1 : 0;
   {
     ProfScope ps(KK_CG_ALPHA, s);
-    hipLaunchKernelGGL(k_cg_alpha, dim3((unsigned)(cg.lat_parts + groups)), dim3(kBlock), cg_vec_lds(C), s, u, bu,
-                       m, C, scale, cg.lat_parts, (const double*)cg.pp, cg.ntiles, cg.alpha);
+    const size_t lds = fold ? std::max(cg_vec_lds(C), sizeof(double) * kFold * C) : cg_vec_lds(C);
+    hipLaunchKernelGGL(k_cg_alpha, dim3((unsigned)blocks), dim3(kBlock), lds, s, u, bu, m, C, scale,
+                       cg.lat_parts, (const double*)cg.pp, cg.ntiles, cg.alpha, fold);
     SGP_LAUNCH_CHECK("k_cg_alpha");
   }
-  {
+  if (!fold) {
     ProfScope ps(KK_CG_SCALAR, s);
     hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, s, cg.alpha, C);
     SGP_LAUNCH_CHECK("k_cg_scalar");

@@ -213,8 +213,9 @@ struct SplatArgs {
 // read once here anyway, so x and p move without a pass of their own. Each
 // element is read and written by the one thread that stages it; the new p
 // is what the tile splats.
-// DIR: the fused variant; it is launched only where the tile's values are
-// whole 16-byte vectors of C == G columns in internal order (vec_v).
+// DIR: the fused variant; it is launched only where a tile's values are
+// all C == G columns of the direction in internal order (and whole 16-byte
+// vectors, vec_v, where the shape stages vectors).
 // pp (CG, else null): row t receives pp_scale * p.p of tile t per column,
 // from the staged values.
 template <typename TU, int G, bool DIR>
@@ -350,10 +351,25 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
         }
       }
     } else {
+      const int64_t p0 = (item / a.chunks) * a.P;
 #pragma unroll
       for (int u = 0; u < S::VPT; ++u) {
         const int f = tid + u * kSplatBlock;
-        if (f < cur_ne / a.D * G) lv[(f / G) * S::RS + f % G] = v[u];
+        if (f < cur_ne / a.D * G) {
+          TU x = v[u];
+          if constexpr (DIR && sizeof(TU) == 8 && !S::VEC) {
+            // the direction update element by element (C == G here)
+            const int c = f % G;
+            const int64_t e = p0 * a.C + f;
+            const TU pold = x;
+            const double rv = __builtin_nontemporal_load((const TU*)up.r + e);
+            const float xv = __builtin_nontemporal_load(up.x + e);
+            x = up.st->active[c] ? (TU)__builtin_fma(up.st->beta[c], (double)pold, rv) : pold;
+            __builtin_nontemporal_store(x, (TU*)up.p + e);
+            __builtin_nontemporal_store((float)__builtin_fma(up.st->alpha[c], (double)pold, (double)xv), up.x + e);
+          }
+          lv[(f / G) * S::RS + f % G] = x;
+        }
       }
     }
 #pragma unroll
@@ -1312,7 +1328,8 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   double* pp = cgm ? cgm->pp : nullptr;
   // the previous CG iteration's direction update: in this splat where its
   // values are whole vectors of all C columns, else as a pass of its own
-  const bool dir_fused = up && sizeof(TU) == 8 && TileShape<TU, G, kSplatBlock>::VEC && sa.vec_v;
+  const bool dir_fused = up && sizeof(TU) == 8 && !perm && C == G &&
+                         (!TileShape<TU, G, kSplatBlock>::VEC || sa.vec_v);
   if (up && !dir_fused) {
     const int rc = launch_cg_dir(*up, (int64_t)L->n * C, C, s);
     if (rc) return rc;

@@ -515,13 +515,15 @@ def test_cg_graph_replay_matches_launches(sgp, tol, max_iter):
 
 @pytest.mark.parametrize("seed,n,d,C,tol,max_iter", [(61, 20000, 6, 16, 0.0, 20), (62, 9000, 4, 4, 1e-5, 400),
                                                      (63, 5000, 3, 5, 1e-4, 300), (64, 3000, 5, 1, 0.0, 13),
-                                                     (65, 12000, 7, 32, 0.0, 11), (66, 4000, 2, 8, 1e-6, 600)])
+                                                     (65, 12000, 7, 32, 0.0, 11), (66, 4000, 2, 8, 1e-6, 600),
+                                                     (67, 6000, 3, 2, 1e-5, 300)])
 def test_cg_fused_direction_update_matches_pass(sgp, seed, n, d, C, tol, max_iter):
     """The CG direction update run inside the next splat gives bitwise the
     same iterates, iteration counts and residuals as its own pass, with
     columns that stop at different iterations, widths that take the fused
-    path (C = 4, 8, 16, 32) and widths that fall back to the pass (C = 1,
-    5), and graph replay on."""
+    path (C = 4, 8, 16, 32 as 16-byte vectors, C = 1, 2 element by element)
+    and a width that falls back to the pass (C = 5: its channel chunk is
+    wider than C), and graph replay on."""
     _note(f"cg fused direction update seed={seed} n={n} d={d} C={C} tol={tol}")
     c = workloads.small_case(seed, n, d, channels=C, kind="mixture")
     lat = sgp.lattice_build(_cuda(c.X), c.lengthscales)
