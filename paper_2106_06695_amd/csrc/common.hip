@@ -36,6 +36,7 @@ const Tuning& tuning() {
     if (k.slice_lds_budget > 163840) k.slice_lds_budget = 163840;
     k.blocks_per_cu = env_int("SGP_TILE_BLOCKS_PER_CU", 0);
     if (k.blocks_per_cu < 0) k.blocks_per_cu = 0;
+    k.blur_seq = env_int("SGP_BLUR_SEQ", 1) != 0;
     return k;
   }();
   return t;
@@ -474,6 +475,7 @@ bool profiling() {
 }
 bool cg_graphs_enabled() { return g_cg_graph.load() != 0; }
 bool blur_fuse_enabled() { return g_blur_fuse.load() != 0; }
+bool blur_seq_enabled() { return tuning().blur_seq; }
 bool cg_fuse_enabled() { return g_cg_fuse.load() != 0; }
 hipStream_t capture_stream() {
   constexpr int kMaxDevices = 64;

@@ -714,6 +714,8 @@ struct Blur2Args {
   int chains;
   int sum_out;
   int split;  // two chains with outputs of their own: the grid's halves take one each
+  int chain0; // k_blur2_split: the first half's chain
+  int halves; // k_blur2_split: 2 (both chains) or 1 (chain0 alone)
   int vec;
   int nt;     // as in BlurArgs
   int64_t rows_per_block;
@@ -842,9 +844,10 @@ __global__ __launch_bounds__(kBlock) void k_blur2_split(Blur2Args<TU> a) {
   constexpr int LPR = G / VW;
   constexpr int R = kBlock / LPR;
   const int sub = threadIdx.x % LPR;
-  const unsigned nb = gridDim.x / 2;
-  const int chain = blockIdx.x >= nb ? 1 : 0;
-  const unsigned bid = blockIdx.x - chain * nb;
+  const unsigned nb = gridDim.x / a.halves;
+  const int half = blockIdx.x >= nb ? 1 : 0;
+  const int chain = a.chain0 + half;
+  const unsigned bid = blockIdx.x - half * nb;
   const int64_t j0 = xcd_block(bid, nb) * a.rows_per_block;
   const int64_t j1 = j0 + a.rows_per_block < a.m ? j0 + a.rows_per_block : a.m;
   for (int64_t j = j0 + threadIdx.x / LPR; j < j1; j += R) {
@@ -1395,6 +1398,28 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
     return chain == 0 ? ((L->blur == SGP_BLUR_REVERSE) ? d - step : step) : d - step;
   };
   const bool fuse = L->order == 1 && blur_fuse_enabled();
+  // Lattice values past the Infinity Cache: the chains' split launches run
+  // one chain after the other (all of chain 0's, then chain 1's), so that a
+  // launch's input and output arrays fit the cache together.
+  const bool seq = fuse && sym && a.nt && blur_seq_enabled();
+  std::vector<Blur2Args<TU>> later;  // chain 1's split launches, in order
+  auto launch2 = [&](const Blur2Args<TU>& b, unsigned grid) -> int {
+    ProfScope ps(KK_BLUR, s);
+    if (b.split)
+      hipLaunchKernelGGL((k_blur2_split<TU, G>), dim3(grid), dim3(kBlock), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_blur2<TU, G>), dim3(grid), dim3(kBlock), 0, s, b);
+    SGP_LAUNCH_CHECK("k_blur2");
+    return SGP_OK;
+  };
+  auto flush_later = [&]() -> int {
+    for (const auto& b : later) {
+      const int rc = launch2(b, bblocks);
+      if (rc) return rc;
+    }
+    later.clear();
+    return SGP_OK;
+  };
   for (int step = 0; step <= d;) {
     TU* dst0 = next0(cur[0]);
     TU* dst1 = next1(cur[1]);
@@ -1413,17 +1438,21 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
       b2.chains = a.chains;
       b2.sum_out = (sym && step + 1 == d) ? 1 : 0;
       b2.split = (a.chains == 2 && !b2.sum_out) ? 1 : 0;
+      b2.chain0 = 0;
+      b2.halves = 2;
       b2.vec = a.vec;
       b2.nt = a.nt;
       b2.rows_per_block = a.rows_per_block;
       for (int t = 0; t < 3; ++t) b2.st[t] = a.st[t];
-      {
-        ProfScope ps(KK_BLUR, s);
-        if (b2.split)
-          hipLaunchKernelGGL((k_blur2_split<TU, G>), dim3(2 * bblocks), dim3(kBlock), 0, s, b2);
-        else
-          hipLaunchKernelGGL((k_blur2<TU, G>), dim3(bblocks), dim3(kBlock), 0, s, b2);
-        SGP_LAUNCH_CHECK("k_blur2");
+      int rc;
+      if (b2.split && seq) {
+        b2.halves = 1;
+        if ((rc = launch2(b2, bblocks))) return rc;
+        b2.chain0 = 1;
+        later.push_back(b2);
+      } else {
+        if ((rc = flush_later())) return rc;
+        if ((rc = launch2(b2, b2.split ? 2 * bblocks : bblocks))) return rc;
       }
       step += 2;
     } else {
@@ -1434,6 +1463,7 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
       a.out[1] = dst1;
       a.nbr[1] = nbr + (int64_t)kdir(step, 1) * T * m;
       a.sum_out = (sym && step == d) ? 1 : 0;
+      if (const int rc = flush_later()) return rc;
       {
         ProfScope ps(KK_BLUR, s);
         hipLaunchKernelGGL((k_blur<TU, G>), dim3(bblocks), dim3(kBlock), 0, s, a);
@@ -1444,6 +1474,7 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
     cur[0] = dst0;
     cur[1] = dst1;
   }
+  if (const int rc = flush_later()) return rc;
   const TU scale = sym ? (TU)(0.5 * (double)L->outputscale) : (TU)L->outputscale;
   if (cgm) {
     // alpha from p.Ap = scale * u.(B u) + noise * p.p, before the slice

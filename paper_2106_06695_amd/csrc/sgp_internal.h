@@ -19,12 +19,13 @@ constexpr int kRedBlocks = 512; // blocks (and partial sums) of the reducing vec
 constexpr int kPiece = 32;      // longest run piece the splat reduces in one go
 
 // Launch-shape knobs of the MVM kernels. Defaults are the measured best on
-// MI355X; SGP_LDS_BUDGET, SGP_SLICE_LDS_BUDGET and SGP_TILE_BLOCKS_PER_CU in
-// the environment override them (read once per process).
+// MI355X; SGP_LDS_BUDGET, SGP_SLICE_LDS_BUDGET, SGP_TILE_BLOCKS_PER_CU and
+// SGP_BLUR_SEQ in the environment override them (read once per process).
 struct Tuning {
   int lds_budget;        // bytes of LDS the splat may stage (one block per CU)
   int slice_lds_budget;  // bytes of LDS the slice may stage (one block per CU)
   int blocks_per_cu;     // resident blocks per CU of the persistent tile kernels (0 = occupancy)
+  bool blur_seq;         // large lattices: the symmetric blur's chains one after the other
 };
 const Tuning& tuning();
 
@@ -72,6 +73,7 @@ bool profiling();
 // Process-wide switch for graph replay of CG iterations.
 bool cg_graphs_enabled();
 bool blur_fuse_enabled();
+bool blur_seq_enabled();
 bool cg_fuse_enabled();
 // A per-thread, per-device stream used only to record graphs.
 hipStream_t capture_stream();
