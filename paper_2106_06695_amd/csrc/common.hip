@@ -36,7 +36,8 @@ const Tuning& tuning() {
     if (k.slice_lds_budget > 163840) k.slice_lds_budget = 163840;
     k.blocks_per_cu = env_int("SGP_TILE_BLOCKS_PER_CU", 0);
     if (k.blocks_per_cu < 0) k.blocks_per_cu = 0;
-    k.blur_seq = env_int("SGP_BLUR_SEQ", 1) != 0;
+    k.blur_seq_mib = env_int("SGP_BLUR_SEQ_MIB", 128);
+    if (k.blur_seq_mib < 0) k.blur_seq_mib = 0;
     return k;
   }();
   return t;
@@ -475,7 +476,10 @@ bool profiling() {
 }
 bool cg_graphs_enabled() { return g_cg_graph.load() != 0; }
 bool blur_fuse_enabled() { return g_blur_fuse.load() != 0; }
-bool blur_seq_enabled() { return tuning().blur_seq; }
+bool blur_seq_for(double bytes) {
+  const int t = tuning().blur_seq_mib;
+  return t > 0 && bytes > (double)t * (1 << 20);
+}
 bool cg_fuse_enabled() { return g_cg_fuse.load() != 0; }
 hipStream_t capture_stream() {
   constexpr int kMaxDevices = 64;

@@ -1398,10 +1398,11 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
     return chain == 0 ? ((L->blur == SGP_BLUR_REVERSE) ? d - step : step) : d - step;
   };
   const bool fuse = L->order == 1 && blur_fuse_enabled();
-  // Lattice values past the Infinity Cache: the chains' split launches run
-  // one chain after the other (all of chain 0's, then chain 1's), so that a
-  // launch's input and output arrays fit the cache together.
-  const bool seq = fuse && sym && a.nt && blur_seq_enabled();
+  // Large lattices (the four value arrays over 128 MiB by default, half the
+  // Infinity Cache): the chains' split launches run one chain after the
+  // other (all of chain 0's, then chain 1's), so that a launch's input and
+  // output arrays sit in the cache together.
+  const bool seq = fuse && sym && blur_seq_for(4.0 * (double)mC * sizeof(TU));
   std::vector<Blur2Args<TU>> later;  // chain 1's split launches, in order
   auto launch2 = [&](const Blur2Args<TU>& b, unsigned grid) -> int {
     ProfScope ps(KK_BLUR, s);

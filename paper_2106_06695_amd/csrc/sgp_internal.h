@@ -20,12 +20,13 @@ constexpr int kPiece = 32;      // longest run piece the splat reduces in one go
 
 // Launch-shape knobs of the MVM kernels. Defaults are the measured best on
 // MI355X; SGP_LDS_BUDGET, SGP_SLICE_LDS_BUDGET, SGP_TILE_BLOCKS_PER_CU and
-// SGP_BLUR_SEQ in the environment override them (read once per process).
+// SGP_BLUR_SEQ_MIB in the environment override them (read once per process).
 struct Tuning {
   int lds_budget;        // bytes of LDS the splat may stage (one block per CU)
   int slice_lds_budget;  // bytes of LDS the slice may stage (one block per CU)
   int blocks_per_cu;     // resident blocks per CU of the persistent tile kernels (0 = occupancy)
-  bool blur_seq;         // large lattices: the symmetric blur's chains one after the other
+  int blur_seq_mib;      // the symmetric blur's chains run one after the other when the four
+                         // lattice value arrays exceed this many MiB (0: never)
 };
 const Tuning& tuning();
 
@@ -73,7 +74,9 @@ bool profiling();
 // Process-wide switch for graph replay of CG iterations.
 bool cg_graphs_enabled();
 bool blur_fuse_enabled();
-bool blur_seq_enabled();
+// True when the symmetric blur should run its chains one after the other
+// for lattice value arrays of `bytes` in all (four arrays).
+bool blur_seq_for(double bytes);
 bool cg_fuse_enabled();
 // A per-thread, per-device stream used only to record graphs.
 hipStream_t capture_stream();
