@@ -9,9 +9,12 @@
 // gives it. For the RBF kernel k' = -k/2, so K' is -1/2 times the lattice
 // operator. Then dL/dx = dL/dz / l and dL/dlog l_p = -sum_n z_np dL/dz_np.
 //
-// Everything runs in the lattice's internal point order and in fp64; the
-// columns are filtered one at a time, so the work buffers hold 2(d+1)
-// channels.
+// Everything runs in the lattice's internal point order. The channels are
+// formed and combined in fp64 and filtered in fp32 (as the forward MVM:
+// fp32 weights and values, fp32 lattice accumulation); the columns are
+// filtered kb at a time (kb * 2(d+1) <= 128 channels per MVM), so that the
+// MVMs share their index and weight reads.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -24,37 +27,41 @@ struct InvEll {
   double v[kMaxD];
 };
 
-// H[i][j], j < 2(d+1): v, z_1 v .. z_d v, g, z_1 g .. z_d g for column c.
+// H[i][b * 2(d+1) + j], j < 2(d+1): v, z_1 v .. z_d v, g, z_1 g .. z_d g
+// for column c0 + b, b < kb (formed in fp64, stored in fp32).
 __global__ __launch_bounds__(kBlock) void k_grad_channels(const float* __restrict__ X,
                                                           const float* __restrict__ V,
                                                           const float* __restrict__ G,
                                                           const uint32_t* __restrict__ perm,
-                                                          int64_t n, int d, int C, int c, InvEll ie,
-                                                          double* __restrict__ H) {
-  const int D = d + 1, CH = 2 * D;
-  const int64_t total = n * CH;
+                                                          int64_t n, int d, int C, int c0, int kb,
+                                                          InvEll ie, float* __restrict__ H) {
+  const int D = d + 1, CH = 2 * D, W = kb * CH;
+  const int64_t total = n * W;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
-    const int64_t i = q / CH;
-    const int j = (int)(q - i * CH);
+    const int64_t i = q / W;
+    const int bj = (int)(q - i * W);
+    const int b = bj / CH, j = bj - b * CH;
     const int64_t src = perm[i];
     const int half = j < D ? 0 : 1;
     const int jj = j - half * D;
+    const int c = c0 + b;
     const double a = half ? (double)G[src * C + c] : (double)V[src * C + c];
-    H[q] = jj == 0 ? a : a * ((double)X[src * d + (jj - 1)] * ie.v[jj - 1]);
+    H[q] = (float)(jj == 0 ? a : a * ((double)X[src * d + (jj - 1)] * ie.v[jj - 1]));
   }
 }
 
 // dz[i][p] += -(g (z Kv - Kzv) + v (z Kg - Kzg)) with K = outputscale * K_lat
-// (the factor 2 of the derivative and the -1/2 of k' cancel).
+// (the factor 2 of the derivative and the -1/2 of k' cancel), for columns
+// c0 .. c0 + kb - 1 in order, in fp64.
 __global__ __launch_bounds__(kBlock) void k_grad_accum(const float* __restrict__ X,
                                                        const float* __restrict__ V,
                                                        const float* __restrict__ G,
                                                        const uint32_t* __restrict__ perm,
-                                                       const double* __restrict__ O, int64_t n,
-                                                       int d, int C, int c, InvEll ie,
+                                                       const float* __restrict__ O, int64_t n,
+                                                       int d, int C, int c0, int kb, InvEll ie,
                                                        double* __restrict__ dz) {
-  const int D = d + 1, CH = 2 * D;
+  const int D = d + 1, CH = 2 * D, W = kb * CH;
   const int64_t total = n * d;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
@@ -62,9 +69,13 @@ __global__ __launch_bounds__(kBlock) void k_grad_accum(const float* __restrict__
     const int p = (int)(q - i * d);
     const int64_t src = perm[i];
     const double z = (double)X[src * d + p] * ie.v[p];
-    const double v = V[src * C + c], g = G[src * C + c];
-    const double* o = O + i * CH;
-    dz[q] -= g * (z * o[0] - o[1 + p]) + v * (z * o[D] - o[D + 1 + p]);
+    double acc = dz[q];
+    for (int b = 0; b < kb; ++b) {
+      const double v = V[src * C + c0 + b], g = G[src * C + c0 + b];
+      const float* o = O + i * W + b * CH;
+      acc -= g * (z * (double)o[0] - (double)o[1 + p]) + v * (z * (double)o[D] - (double)o[D + 1 + p]);
+    }
+    dz[q] = acc;
   }
 }
 
@@ -152,7 +163,8 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
         if (b[k]) dev_release(b[k], s);
     }
   } guard{bufs, s};
-  const size_t sizes[4] = {sizeof(double) * n * CH, sizeof(double) * n * CH, sizeof(double) * n * d,
+  const int kb = std::max(1, std::min((int)C, 128 / CH));  // columns per MVM
+  const size_t sizes[4] = {sizeof(float) * n * kb * CH, sizeof(float) * n * kb * CH, sizeof(double) * n * d,
                            sizeof(double) * kColBlocks * d};
   for (int k = 0; k < 4; ++k) {
     hipError_t e = pool_alloc(&bufs[k], sizes[k], s);
@@ -163,25 +175,26 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
       return e == hipErrorOutOfMemory ? SGP_ENOMEM : SGP_EHIP;
     }
   }
-  double* H = (double*)bufs[0];
-  double* O = (double*)bufs[1];
+  float* H = (float*)bufs[0];
+  float* O = (float*)bufs[1];
   double* dz = (double*)bufs[2];
   double* part = (double*)bufs[3];
   const uint32_t* perm = (const uint32_t*)L->perm.ptr;
   int rc;
   if ((rc = launch_fill_u32((uint32_t*)dz, (size_t)n * d * 2, 0u, s))) return rc;
-  for (int c = 0; c < C; ++c) {
+  for (int c0 = 0; c0 < C; c0 += kb) {
+    const int nb = std::min(kb, (int)C - c0);
     {
       ProfScope ps(KK_GRAD, s);
-      hipLaunchKernelGGL(k_grad_channels, dim3(grid_for_g(n * CH)), dim3(kBlock), 0, s, X, V, G, perm,
-                         n, d, (int)C, c, ie, H);
+      hipLaunchKernelGGL(k_grad_channels, dim3(grid_for_g(n * nb * CH)), dim3(kBlock), 0, s, X, V, G, perm,
+                         n, d, (int)C, c0, nb, ie, H);
       SGP_LAUNCH_CHECK("k_grad_channels");
     }
-    if ((rc = mvm_f64(L, H, CH, O, s))) return rc;
+    if ((rc = mvm_f32(L, H, nb * CH, O, s))) return rc;
     {
       ProfScope ps(KK_GRAD, s);
       hipLaunchKernelGGL(k_grad_accum, dim3(grid_for_g(n * d)), dim3(kBlock), 0, s, X, V, G, perm, O,
-                         n, d, (int)C, c, ie, dz);
+                         n, d, (int)C, c0, nb, ie, dz);
       SGP_LAUNCH_CHECK("k_grad_accum");
     }
   }

@@ -491,28 +491,28 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 
 // U[j] = sum of lattice point j's partial rows occ_ptr[j] .. occ_ptr[j+1]-1
 // (one per piece of a run touching it, contiguous; row_vert names each row's
-// lattice point). The rows are cut into ranges of kGatherRows; a group of G
-// lanes adds its range's rows in order, eight rows loaded at a time.
+// lattice point). The rows are cut into ranges of R rows (gather_rows); a
+// group of G lanes adds its range's rows in order, eight rows loaded at a
+// time.
 // A lattice point whose rows lie in one range is written directly; the part
 // of a longer one that a range holds becomes a fragment (slot 0: it starts
 // the range; slot 1: it ends the range), summed in range order by
 // k_gather_fix. The work per group is fixed, whatever the list lengths.
-constexpr int kGatherRows = 64;
 // VW channels per lane (16-byte loads when the rows allow), G / VW lanes per
 // group; every channel's rows are added in the same order for any VW.
 template <typename TU, int G, int VW>
 __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restrict__ row_vert,
                                                          const TU* __restrict__ part,
                                                          TU* __restrict__ U, TU* __restrict__ frag,
-                                                         int64_t nrows, int C, int64_t ngroups) {
+                                                         int64_t nrows, int C, int64_t ngroups, int R) {
   constexpr int LG = G / VW;       // lanes per group
   constexpr int GPB = kBlock / LG;  // groups per block
   constexpr int B = 8;              // rows loaded together
   const int lane = threadIdx.x % LG;
   const int64_t gi = xcd_block(blockIdx.x, gridDim.x) * GPB + threadIdx.x / LG;
   if (gi >= ngroups) return;
-  const int64_t o0 = gi * kGatherRows;
-  const int64_t o1 = o0 + kGatherRows < nrows ? o0 + kGatherRows : nrows;
+  const int64_t o0 = gi * R;
+  const int64_t o1 = o0 + R < nrows ? o0 + R : nrows;
   // a segment is a whole lattice point unless it touches a range edge that
   // its lattice point continues across
   const int32_t before = o0 > 0 ? row_vert[o0 - 1] : -1;
@@ -564,18 +564,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_fix(const int32_t* __restrict
                                                        const int32_t* __restrict__ occ_ptr,
                                                        const void* __restrict__ frag_v,
                                                        void* __restrict__ U_v, int64_t ngroups, int C,
-                                                       int elem) {
+                                                       int elem, int R) {
   const int64_t total = ngroups * C;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
     const int64_t g1 = q / C;
     const int c = (int)(q - g1 * C);
     if (g1 == 0) continue;
-    const int64_t j = row_vert[g1 * kGatherRows];
+    const int64_t j = row_vert[g1 * R];
     const int64_t js = occ_ptr[j], je = occ_ptr[j + 1];
-    const int64_t g0 = js / kGatherRows;
-    if (g0 == g1 || (je - 1) / kGatherRows != g1) continue;  // starts here, or ends further on
-    const int64_t first = (g0 * 2 + (js == g0 * kGatherRows ? 0 : 1)) * C + c;
+    const int64_t g0 = js / R;
+    if (g0 == g1 || (je - 1) / R != g1) continue;  // starts here, or ends further on
+    const int64_t first = (g0 * 2 + (js == g0 * R ? 0 : 1)) * C + c;
     if (elem == 8) {
       const double* frag = (const double*)frag_v;
       double acc = frag[first];
@@ -1271,7 +1271,18 @@ unsigned persistent_grid(const void* kernel, int threads, size_t lds, int64_t it
   return (unsigned)g;
 }
 
-int64_t gather_ranges(const sgp_lattice* L) { return (L->npiece + kGatherRows - 1) / kGatherRows; }
+// Rows per gather range: 64, halved (down to 8) while the lattice would
+// have fewer than 4096 ranges, so that a small lattice's gather still
+// spreads over the GPU instead of summing long ranges in few groups.
+int gather_rows(const sgp_lattice* L) {
+  int r = 64;
+  while (r > 8 && (L->npiece + r - 1) / r < 4096) r >>= 1;
+  return r;
+}
+int64_t gather_ranges(const sgp_lattice* L) {
+  const int r = gather_rows(L);
+  return (L->npiece + r - 1) / r;
+}
 
 unsigned grid_cap(int64_t work) {
   int64_t b = (work + kBlock - 1) / kBlock;
@@ -1356,21 +1367,22 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   }
   {
     ProfScope ps(KK_SPLAT_GATHER, s);
-    const int64_t ngroups = (L->npiece + kGatherRows - 1) / kGatherRows;
+    const int R = gather_rows(L);
+    const int64_t ngroups = gather_ranges(L);
     constexpr int VWG = 16 / (int)sizeof(TU);  // channels per lane with 16-byte loads
     if (G % VWG == 0 && C % VWG == 0 && aligned16(part) && aligned16(U0) && aligned16(frag)) {
       const int64_t blocks = (ngroups + kBlock / (G / VWG) - 1) / (kBlock / (G / VWG));
       hipLaunchKernelGGL((k_splat_gather<TU, G, (G % VWG == 0 ? VWG : 1)>), dim3((unsigned)blocks), dim3(kBlock),
-                         0, s, (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups);
+                         0, s, (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups, R);
     } else {
       const int64_t blocks = (ngroups + kBlock / G - 1) / (kBlock / G);
       hipLaunchKernelGGL((k_splat_gather<TU, G, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                         (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups);
+                         (const int32_t*)L->row_vert.ptr, part, U0, frag, L->npiece, C, ngroups, R);
     }
     SGP_LAUNCH_CHECK("k_splat_gather");
     hipLaunchKernelGGL(k_gather_fix, dim3(grid_cap(ngroups * C)), dim3(kBlock), 0, s,
                        (const int32_t*)L->row_vert.ptr, (const int32_t*)L->occ_ptr.ptr, (const void*)frag,
-                       (void*)U0, ngroups, C, (int)sizeof(TU));
+                       (void*)U0, ngroups, C, (int)sizeof(TU), R);
     SGP_LAUNCH_CHECK("k_gather_fix");
   }
 
@@ -1575,6 +1587,10 @@ int mvm_cg(const sgp_lattice* L, double* p, int C, hipStream_t s, double noise, 
 
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s) {
   return mvm_dispatch<double>(L, V, nullptr, C, out, s, 0.0, nullptr);
+}
+
+int mvm_f32(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s) {
+  return mvm_dispatch<float>(L, V, nullptr, C, out, s, 0.f, nullptr);
 }
 
 // Times every candidate launch choice on this lattice and keeps the fastest

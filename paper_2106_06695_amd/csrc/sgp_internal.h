@@ -236,4 +236,6 @@ int mvm_cg(const sgp_lattice* L, double* p, int C, hipStream_t s, double noise, 
            const CgDirUpdate* up);
 // fp64 values and accumulation, internal point order, no epilogue
 int mvm_f64(const sgp_lattice* L, const double* V, int C, double* out, hipStream_t s);
+// fp32 values and accumulation, internal point order
+int mvm_f32(const sgp_lattice* L, const float* V, int C, float* out, hipStream_t s);
 }  // namespace sgp

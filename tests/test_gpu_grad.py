@@ -1,6 +1,8 @@
 """GPU adjoint of the lattice MVM (Section 4.2) against the oracle's
 k'-filtering gradient, and the autograd wrapper. Bar: relative 2-norm error
-<= 1e-4 on dX and on dlog(l); both sides filter in fp64."""
+<= 1e-4 on dX and on dlog(l). The oracle filters in fp64; the GPU forms and
+combines the filtering channels in fp64 and filters them in fp32, as its
+forward MVM does."""
 import sys
 
 import numpy as np
