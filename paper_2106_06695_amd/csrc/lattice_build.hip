@@ -1191,10 +1191,11 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
   // tile size: at most 256 points (a point index fits 8 bits) and 4096
   // entries (the tile kernels stage a tile's entries in LDS); a multiple of
   // 4, so that every tile's entries start 4-byte aligned in the 8- and
-  // 16-bit arrays. Small inputs get smaller tiles (down to 32 points) until
-  // there are 512, so that the tile kernels still spread over the GPU.
-  int P = std::min(256, 4096 / D) & ~3;
-  while (P / 2 >= 32 && (n + P - 1) / P < 512) P = (P / 2) & ~3;
+  // 16-bit arrays. (Smaller tiles for small inputs were measured and not
+  // kept: a tile kernel's time on few tiles is the latency of one tile,
+  // whatever its size, and the slice, one block per CU, then takes several
+  // tiles per block.)
+  const int P = std::min(256, 4096 / D) & ~3;
   if (P > 3 * (kInsEntries / D)) {  // k_tile_order follows at most three hashing groups per tile
     set_error("lattice_build: internal tile shape error (d = %d)", d);
     return SGP_EINVAL;
