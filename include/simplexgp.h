@@ -240,6 +240,16 @@ int sgp_cg_graph_enable(int on);
  * setting. */
 int sgp_blur_fuse_enable(int on);
 
+/* Sequential chains of the symmetric blur (process-wide). When the four
+ * lattice value arrays of an MVM exceed `bytes` in all, the fused launches
+ * that advance the forward and the reverse chain separately run one chain
+ * after the other (all of one chain's, then the other's) instead of both
+ * chains in one launch, so that a launch's arrays share the Infinity Cache.
+ * Every row is computed as before, so results are bitwise identical for any
+ * setting. bytes < 0: never. The default is SGP_BLUR_SEQ_MIB MiB from the
+ * environment, else 128 MiB. Returns the previous threshold. */
+int64_t sgp_blur_seq_bytes(int64_t bytes);
+
 /* CG direction update fused into the splat (process-wide switch, default
  * on). Each iteration's x += alpha p and p = r + beta p (Section 2, the
  * conjugate-gradient recurrence) then run in the next iteration's splat,

@@ -25,7 +25,7 @@ from . import _lib
 __all__ = [
     "SGPError", "Lattice", "lattice_build", "lattice_mvm", "cg_solve", "lattice_mvm_grad",
     "lattice_info", "lattice_export", "lattice_free", "lattice_kernel_mvm", "profile",
-    "library_path", "cg_graph_enable", "blur_fuse_enable", "autotune", "autotune_reset",
+    "library_path", "cg_graph_enable", "blur_fuse_enable", "blur_seq_bytes", "autotune", "autotune_reset",
     "set_allocator", "use_torch_allocator",
 ]
 
@@ -303,6 +303,14 @@ def blur_fuse_enable(on: bool) -> bool:
     """Turn fused two-step blur launches on or off (process-wide); returns
     the previous setting. Results do not depend on it."""
     return bool(_lib.load().sgp_blur_fuse_enable(1 if on else 0))
+
+
+def blur_seq_bytes(nbytes: int) -> int:
+    """Set the size of the four lattice value arrays above which the
+    symmetric blur runs its two chains one after the other (process-wide;
+    negative: never); returns the previous threshold. Results do not depend
+    on it."""
+    return int(_lib.load().sgp_blur_seq_bytes(int(nbytes)))
 
 
 def autotune(lat: Lattice, C: int, fp64: bool = True, reps: int = 3) -> dict:

@@ -36,6 +36,7 @@ SIGNATURES = {
     "sgp_debug_inject_oom": (ctypes.c_int, [_I32]),
     "sgp_cg_graph_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_blur_fuse_enable": (ctypes.c_int, [ctypes.c_int]),
+    "sgp_blur_seq_bytes": (ctypes.c_int64, [ctypes.c_int64]),
     "sgp_cg_fuse_enable": (ctypes.c_int, [ctypes.c_int]),
     "sgp_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),

@@ -476,9 +476,13 @@ bool profiling() {
 }
 bool cg_graphs_enabled() { return g_cg_graph.load() != 0; }
 bool blur_fuse_enabled() { return g_blur_fuse.load() != 0; }
+std::atomic<int64_t>& blur_seq_threshold() {
+  static std::atomic<int64_t> t{tuning().blur_seq_mib > 0 ? (int64_t)tuning().blur_seq_mib << 20 : -1};
+  return t;
+}
 bool blur_seq_for(double bytes) {
-  const int t = tuning().blur_seq_mib;
-  return t > 0 && bytes > (double)t * (1 << 20);
+  const int64_t t = blur_seq_threshold().load();
+  return t >= 0 && bytes > (double)t;
 }
 bool cg_fuse_enabled() { return g_cg_fuse.load() != 0; }
 hipStream_t capture_stream() {
@@ -622,6 +626,7 @@ int sgp_debug_inject_oom(int32_t count) {
 int sgp_cg_graph_enable(int on) { return g_cg_graph.exchange(on != 0 ? 1 : 0); }
 int sgp_cg_fuse_enable(int on) { return g_cg_fuse.exchange(on != 0 ? 1 : 0); }
 int sgp_blur_fuse_enable(int on) { return g_blur_fuse.exchange(on != 0 ? 1 : 0); }
+int64_t sgp_blur_seq_bytes(int64_t bytes) { return blur_seq_threshold().exchange(bytes < 0 ? -1 : bytes); }
 
 int sgp_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

@@ -25,8 +25,7 @@ struct Tuning {
   int lds_budget;        // bytes of LDS the splat may stage (one block per CU)
   int slice_lds_budget;  // bytes of LDS the slice may stage (one block per CU)
   int blocks_per_cu;     // resident blocks per CU of the persistent tile kernels (0 = occupancy)
-  int blur_seq_mib;      // the symmetric blur's chains run one after the other when the four
-                         // lattice value arrays exceed this many MiB (0: never)
+  int blur_seq_mib;      // initial threshold of sgp_blur_seq_bytes in MiB (0: never)
 };
 const Tuning& tuning();
 

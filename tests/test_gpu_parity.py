@@ -461,6 +461,31 @@ def test_blur_fused_matches_unfused(sgp, blur, seed, n, d, C):
         lat.free()
 
 
+@pytest.mark.parametrize("seed,n,d,C", [(95, 30000, 11, 16), (96, 9000, 6, 3), (97, 12000, 4, 8)])
+def test_blur_sequential_chains_match(sgp, seed, n, d, C):
+    """The symmetric blur's two chains run one after the other (as for large
+    lattices) give bitwise the same MVM (fp32) and CG iterates (fp64) as both
+    chains in one launch, with d + 1 even and odd."""
+    _note(f"blur sequential chains seed={seed} n={n} d={d} C={C}")
+    c = workloads.small_case(seed, n, d, channels=C, kind="mixture")
+    lat = sgp.lattice_build(_cuda(c.X), c.lengthscales)
+    V = _cuda(c.values)
+    prev = sgp.blur_seq_bytes(-1)
+    try:
+        y0 = sgp.lattice_mvm(lat, V).cpu().numpy()
+        x0, it0, rel0 = sgp.cg_solve(lat, V, 0.1, 0.0, max_iter=6)
+        x0 = x0.cpu().numpy()
+        sgp.blur_seq_bytes(0)
+        y1 = sgp.lattice_mvm(lat, V).cpu().numpy()
+        x1, it1, rel1 = sgp.cg_solve(lat, V, 0.1, 0.0, max_iter=6)
+        np.testing.assert_array_equal(y1, y0)
+        np.testing.assert_array_equal(x1.cpu().numpy(), x0)
+        np.testing.assert_array_equal(rel1, rel0)
+    finally:
+        sgp.blur_seq_bytes(prev)
+        lat.free()
+
+
 @pytest.mark.parametrize("C,fp64", [(5, True), (16, True), (3, False)])
 def test_autotune_keeps_results(sgp, C, fp64):
     """Autotuned launch shapes give bitwise the same MVM and CG results, and
