@@ -30,6 +30,7 @@
 // round-robin over the 8 XCDs), so tiles that share lattice points share
 // an L2.
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "cg_step.h"
@@ -139,9 +140,16 @@ __device__ __forceinline__ void xcd_items(int64_t items, int64_t* first, int64_t
 // most 256 points and kMaxTileEntries entries and runs per tile).
 constexpr int kMaxTileEntries = 4096;
 constexpr int kSplatBlock = 512;   // two blocks per CU
-constexpr int kSliceBlock = 1024;  // one block per CU
-template <typename TU, int G, int NT>
+// Threads per block of k_slice_tile: 1024 (one block per CU), or for narrow
+// channel chunks just the lane groups for the 256 points of a tile (LPR =
+// G / VW lanes each), so that the lanes are not left idle. The narrow block
+// also stages fewer lattice rows per pass (RC = 8 NT / G), so it is taken
+// only where a tile's runs mostly fit in one pass.
+template <int G>
+constexpr int slice_threads_narrow() { return G >= 16 ? 1024 : G == 8 ? 512 : 256; }
+template <typename TU, int G, int NT_>
 struct TileShape {
+  static constexpr int NT = NT_;
   static constexpr int kPts = 256;
   static constexpr int EPT = kMaxTileEntries / NT;  // entries per thread
   static constexpr int RPT = 2;                      // runs prefetched per thread (splat)
@@ -876,9 +884,9 @@ struct SliceLds {
   size_t w, sl, total;
   int zrow;  // an all-zero lattice row past the staged rows and the reduction area
 };
-template <typename TU, int G>
+template <typename TU, int G, int NT = 1024>
 __host__ __device__ inline SliceLds slice_lds(int P, int D, int maxq) {
-  using S = TileShape<TU, G, kSliceBlock>;
+  using S = TileShape<TU, G, NT>;
   SliceLds o;
   const size_t row = sizeof(TU) * (size_t)S::RS;
   size_t b = row * (size_t)S::RC;
@@ -915,17 +923,17 @@ struct SliceArgs {
 // the staged rows. The CG variant forms q = out + noise * p, moves the
 // residual (out is r: r -= alpha q, alpha already known) and emits the
 // tile's new r . r per column, reduced in a fixed order.
-template <typename TU, int G, bool CG>
+template <typename TU, int G, bool CG, int NT>
 // perm: caller row of each sorted point, or null. CG only: p is the
 // direction and out the residual (sorted order), hook.partials receive each
 // tile's r . r per column, mperm maps sorted points to caller rows for the
 // mrows mask.
-__global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
+__global__ __launch_bounds__(NT) void k_slice_tile(
     const int32_t* __restrict__ tile_off, const int32_t* __restrict__ tile_verts,
     const uint16_t* __restrict__ loc, const float* __restrict__ ws, const TU* __restrict__ U,
     TU* __restrict__ out, const uint32_t* __restrict__ perm, const TU* __restrict__ p,
     CgHook hook, const uint32_t* __restrict__ mperm, SliceArgs<TU> a) {
-  using S = TileShape<TU, G, kSliceBlock>;
+  using S = TileShape<TU, G, NT>;
   extern __shared__ __align__(16) unsigned char smem[];
   TU* lu = (TU*)smem;
   float* lw = (float*)(smem + a.lds.w);
@@ -944,14 +952,14 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
   auto load_index = [&](int r0, int nr, const int32_t* verts) {
 #pragma unroll
     for (int u = 0; u < S::UPT; ++u) {
-      const int r = (tid + u * kSliceBlock) / G;
+      const int r = (tid + u * S::NT) / G;
       vj[u] = verts[r0 + (r < nr ? r : nr - 1)];
     }
   };
   auto load_rows = [&](int ch) {
 #pragma unroll
     for (int u = 0; u < S::UPT; ++u) {
-      const int c = ch * G + (tid + u * kSliceBlock) % G;
+      const int c = ch * G + (tid + u * S::NT) % G;
       ur[u] = U[(int64_t)vj[u] * a.C + (c < a.C ? c : a.C - 1)];
     }
   };
@@ -974,7 +982,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
     const uint16_t* gsl = loc + p0 * a.D;
 #pragma unroll
     for (int u = 0; u < S::EPT; ++u) {
-      const int e = tid + u * kSliceBlock;
+      const int e = tid + u * S::NT;
       w[u] = gw[e < ne ? e : ne - 1];
     }
     // slots in pairs (the tile starts 4-byte aligned; the array has a
@@ -983,7 +991,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
     const int npair = (ne + 1) / 2;
 #pragma unroll
     for (int u = 0; u < S::EPT / 2; ++u) {
-      const int pi = tid + u * kSliceBlock;
+      const int pi = tid + u * S::NT;
       sl2[u] = gsl2[pi < npair ? pi : npair - 1];
     }
     load_rows(ch);
@@ -991,7 +999,7 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
   auto stage_rows = [&](int nr) {
 #pragma unroll
     for (int u = 0; u < S::UPT; ++u) {
-      const int f = tid + u * kSliceBlock;
+      const int f = tid + u * S::NT;
       if (f < nr * G) lu[(f / G) * S::RS + f % G] = ur[u];
     }
   };
@@ -999,11 +1007,11 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
   // CG: alpha of every column (known before this kernel)
   __shared__ TU s_alpha[CG ? kMaxCgCols : 1];
   if constexpr (CG) {
-    for (int c = tid; c < a.C && c < kMaxCgCols; c += kSliceBlock) s_alpha[c] = (TU)hook.st->alpha[c];
+    for (int c = tid; c < a.C && c < kMaxCgCols; c += S::NT) s_alpha[c] = (TU)hook.st->alpha[c];
   }
   int64_t item, end, step;
   xcd_items(a.items, &item, &end, &step);
-  for (int i = tid; i < S::RS; i += kSliceBlock) lu[a.lds.zrow * S::RS + i] = (TU)0;  // the zero row
+  for (int i = tid; i < S::RS; i += S::NT) lu[a.lds.zrow * S::RS + i] = (TU)0;  // the zero row
   if (item < end) {
     fetch_index(item);
     fetch(item);
@@ -1015,12 +1023,12 @@ __global__ __launch_bounds__(kSliceBlock) void k_slice_tile(
     __syncthreads();  // the previous tile is done with the LDS
 #pragma unroll
     for (int u = 0; u < S::EPT; ++u) {
-      const int e = tid + u * kSliceBlock;
+      const int e = tid + u * S::NT;
       if (e < cur_ne) lw[e] = w[u];
     }
 #pragma unroll
     for (int u = 0; u < S::EPT / 2; ++u) {
-      const int pi = tid + u * kSliceBlock;
+      const int pi = tid + u * S::NT;
       if (2 * pi < cur_ne) ((uint32_t*)lsl)[pi] = sl2[u];
     }
     stage_rows(cur_nq < RC ? cur_nq : RC);
@@ -1506,24 +1514,32 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   la.scale = scale;
   la.noise = noise;
   la.mrows = cgm ? L->solve_rows : 0;
-  la.lds = slice_lds<TU, G>(P, D, maxq);
   const int32_t* toff = (const int32_t*)L->tile_off.ptr;
   const int32_t* tverts = (const int32_t*)L->tile_verts.ptr;
   const uint16_t* loc = (const uint16_t*)L->loc.ptr;
   const float* ws = (const float*)L->ws.ptr;
   const uint32_t* mperm = (const uint32_t*)L->perm.ptr;
-  if (cgm) {
-    const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, true>, kSliceBlock, la.lds.total,
-                                          la.items, lc.slice_bpc);
-    hipLaunchKernelGGL((k_slice_tile<TU, G, true>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
-                       tverts, loc, ws, (const TU*)cur[0], out, perm, p, cgm->beta, mperm, la);
-  } else {
-    const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, false>, kSliceBlock, la.lds.total,
-                                          la.items, lc.slice_bpc);
-    hipLaunchKernelGGL((k_slice_tile<TU, G, false>), dim3(grid), dim3(kSliceBlock), la.lds.total, s, toff,
-                       tverts, loc, ws, (const TU*)cur[0], out, perm, (const TU*)nullptr, CgHook{},
-                       mperm, la);
-  }
+  auto launch = [&](auto nt_tag) {
+    constexpr int NT = decltype(nt_tag)::value;
+    la.lds = slice_lds<TU, G, NT>(P, D, maxq);
+    if (cgm) {
+      const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, true, NT>, NT, la.lds.total,
+                                            la.items, lc.slice_bpc);
+      hipLaunchKernelGGL((k_slice_tile<TU, G, true, NT>), dim3(grid), dim3(NT), la.lds.total, s, toff, tverts,
+                         loc, ws, (const TU*)cur[0], out, perm, p, cgm->beta, mperm, la);
+    } else {
+      const unsigned grid = persistent_grid((const void*)&k_slice_tile<TU, G, false, NT>, NT, la.lds.total,
+                                            la.items, lc.slice_bpc);
+      hipLaunchKernelGGL((k_slice_tile<TU, G, false, NT>), dim3(grid), dim3(NT), la.lds.total, s, toff, tverts,
+                         loc, ws, (const TU*)cur[0], out, perm, (const TU*)nullptr, CgHook{}, mperm, la);
+    }
+  };
+  constexpr int NTn = slice_threads_narrow<G>();
+  // the narrow block where the mean run list takes at most 2/3 of its pass
+  if (NTn < 1024 && 3 * L->nrun <= 2 * L->ntiles * (int64_t)TileShape<TU, G, NTn>::RC)
+    launch(std::integral_constant<int, NTn>{});
+  else
+    launch(std::integral_constant<int, 1024>{});
   SGP_LAUNCH_CHECK("k_slice_tile");
   return SGP_OK;
 }

@@ -248,6 +248,32 @@ def test_cg_fixed_iterations_widths(sgp, orc, C, d):
     assert _colerr(x.cpu().numpy(), xo).max() <= CG_TOL
 
 
+@pytest.mark.parametrize("seed,n,d,C,order,kernel,blur,outputscale,noise,iters", [
+    (401, 3000, 4, 3, 2, "rbf", "symmetric", 1.0, 0.1, 10),      # five-tap stencil: unfused blur
+    (402, 2500, 5, 2, 1, "matern32", "symmetric", 1.7, 0.2, 10),
+    (403, 2500, 3, 40, 1, "rbf", "symmetric", 1.0, 0.1, 10),    # two channel chunks
+    (404, 2000, 3, 4, 1, "rbf", "forward", 1.0, 0.5, 4),        # one blur chain, paper order
+    (405, 2000, 6, 1, 1, "rbf", "reverse", 2.5, 0.5, 4),
+])
+def test_cg_operator_variants(sgp, orc, seed, n, d, C, order, kernel, blur, outputscale, noise, iters):
+    """Fixed-iteration CG iterates against the oracle's CG for blur orders,
+    kernels, output scales and channel counts beyond the default: alpha's
+    p.Ap is formed on the lattice (scale u.Bu + noise p.p) and the residual
+    moves in the slice for every one of them. FORWARD and REVERSE are not
+    symmetric; a few iterations of the same recurrence still compare."""
+    _note(f"cg operator variant seed={seed} d={d} C={C} order={order} {kernel} {blur}")
+    c = workloads.small_case(seed, n, d, channels=C, kind="mixture")
+    lat, olat = _build_both(sgp, orc, c.X, c.lengthscales, order=order, kernel=kernel, blur=blur,
+                            outputscale=outputscale)
+    mode = {"symmetric": orc.SYMMETRIC, "forward": orc.FORWARD, "reverse": orc.REVERSE}[blur]
+    x, it, rel = sgp.cg_solve(lat, _cuda(c.values), noise, 0.0, max_iter=iters)
+    xo, ito, relo, _ = olat.cg(c.values.astype(np.float64), noise, 0.0, max_iter=iters, mode=mode,
+                                outputscale=outputscale)
+    assert np.all(it == iters) and np.all(ito == iters)
+    assert _colerr(x.cpu().numpy(), xo).max() <= CG_TOL
+    lat.free()
+
+
 def test_cg_to_tolerance(sgp, orc):
     _note("cg tolerance ws1")
     w = workloads.ws1()
