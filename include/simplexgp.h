@@ -155,10 +155,11 @@ int cg_solve(const sgp_lattice* L, const float* rhs, int32_t C, float noise, flo
  * V, G: n x C fp32 device. dX: n x d fp32 device output (or NULL).
  * dlogell: host array of d doubles (or NULL). The channels are formed and
  * combined in fp64 and filtered in fp32 (as lattice_mvm), up to 128
- * channels (several columns) per filtering. Allocates stream-ordered work
- * memory of about 8 n min(128, 2(d+1)C) + 8 n d bytes plus the lattice's
- * fp32 work buffer for that many channels, and synchronises `stream`. The
- * dV term of the adjoint is K G itself (lattice_mvm). */
+ * channels (several columns) at a time, in narrower MVMs on large lattices.
+ * Allocates stream-ordered work memory of about 8 n min(128, 2(d+1)C) + 8 n d
+ * bytes plus the lattice's fp32 work buffer for one such MVM, and
+ * synchronises `stream`. The dV term of the adjoint is K G itself
+ * (lattice_mvm). */
 int lattice_mvm_grad(const sgp_lattice* L, const float* X, const float* V, const float* G,
                      int32_t C, float* dX, double* dlogell /* host */, void* stream);
 

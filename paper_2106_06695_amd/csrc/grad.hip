@@ -11,9 +11,12 @@
 //
 // Everything runs in the lattice's internal point order. The channels are
 // formed and combined in fp64 and filtered in fp32 (as the forward MVM:
-// fp32 weights and values, fp32 lattice accumulation); the columns are
-// filtered kb at a time (kb * 2(d+1) <= 128 channels per MVM), so that the
-// MVMs share their index and weight reads.
+// fp32 weights and values, fp32 lattice accumulation). The columns are taken
+// kb at a time (kb * 2(d+1) <= 128 channels), whose channels are filtered
+// in blocks of W: all of them in one MVM on a small lattice, narrower blocks
+// on a large one, so that the blur's two lattice arrays (m x W) stay within
+// the Infinity Cache. An MVM's value for a channel does not depend on the
+// other channels, so the results do not depend on W.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -27,27 +30,38 @@ struct InvEll {
   double v[kMaxD];
 };
 
-// H[i][b * 2(d+1) + j], j < 2(d+1): v, z_1 v .. z_d v, g, z_1 g .. z_d g
-// for column c0 + b, b < kb (formed in fp64, stored in fp32).
+// Channel bj of point i in blocks of W channels: [bj / W][i][bj % W].
+__host__ __device__ inline int64_t chan_at(int64_t n, int W, int64_t i, int bj) {
+  return (int64_t)(bj / W) * n * W + i * W + bj % W;
+}
+
+// Channel bj = b * 2(d+1) + j, j < 2(d+1), of column c0 + b (b < kb): v,
+// z_1 v .. z_d v, g, z_1 g .. z_d g, formed in fp64 and stored in fp32 at
+// chan_at; channels past kb * 2(d+1) up to nblk * W are zero.
 __global__ __launch_bounds__(kBlock) void k_grad_channels(const float* __restrict__ X,
                                                           const float* __restrict__ V,
                                                           const float* __restrict__ G,
                                                           const uint32_t* __restrict__ perm,
                                                           int64_t n, int d, int C, int c0, int kb,
-                                                          InvEll ie, float* __restrict__ H) {
-  const int D = d + 1, CH = 2 * D, W = kb * CH;
-  const int64_t total = n * W;
+                                                          int W, int nblk, InvEll ie,
+                                                          float* __restrict__ H) {
+  const int D = d + 1, CH = 2 * D, K = kb * CH, KW = nblk * W;
+  const int64_t total = n * KW;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
-    const int64_t i = q / W;
-    const int bj = (int)(q - i * W);
-    const int b = bj / CH, j = bj - b * CH;
-    const int64_t src = perm[i];
-    const int half = j < D ? 0 : 1;
-    const int jj = j - half * D;
-    const int c = c0 + b;
-    const double a = half ? (double)G[src * C + c] : (double)V[src * C + c];
-    H[q] = (float)(jj == 0 ? a : a * ((double)X[src * d + (jj - 1)] * ie.v[jj - 1]));
+    const int64_t i = q / KW;
+    const int bj = (int)(q - i * KW);
+    float h = 0.f;
+    if (bj < K) {
+      const int b = bj / CH, j = bj - b * CH;
+      const int64_t src = perm[i];
+      const int half = j < D ? 0 : 1;
+      const int jj = j - half * D;
+      const int c = c0 + b;
+      const double a = half ? (double)G[src * C + c] : (double)V[src * C + c];
+      h = (float)(jj == 0 ? a : a * ((double)X[src * d + (jj - 1)] * ie.v[jj - 1]));
+    }
+    H[chan_at(n, W, i, bj)] = h;
   }
 }
 
@@ -59,9 +73,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_accum(const float* __restrict__
                                                        const float* __restrict__ G,
                                                        const uint32_t* __restrict__ perm,
                                                        const float* __restrict__ O, int64_t n,
-                                                       int d, int C, int c0, int kb, InvEll ie,
+                                                       int d, int C, int c0, int kb, int W, InvEll ie,
                                                        double* __restrict__ dz) {
-  const int D = d + 1, CH = 2 * D, W = kb * CH;
+  const int D = d + 1, CH = 2 * D;
   const int64_t total = n * d;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
@@ -72,8 +86,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_accum(const float* __restrict__
     double acc = dz[q];
     for (int b = 0; b < kb; ++b) {
       const double v = V[src * C + c0 + b], g = G[src * C + c0 + b];
-      const float* o = O + i * W + b * CH;
-      acc -= g * (z * (double)o[0] - (double)o[1 + p]) + v * (z * (double)o[D] - (double)o[D + 1 + p]);
+      const int bj = b * CH;
+      const double o0 = O[chan_at(n, W, i, bj)], op = O[chan_at(n, W, i, bj + 1 + p)];
+      const double oD = O[chan_at(n, W, i, bj + D)], oDp = O[chan_at(n, W, i, bj + D + 1 + p)];
+      acc -= g * (z * o0 - op) + v * (z * oD - oDp);
     }
     dz[q] = acc;
   }
@@ -163,9 +179,15 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
         if (b[k]) dev_release(b[k], s);
     }
   } guard{bufs, s};
-  const int kb = std::max(1, std::min((int)C, 128 / CH));  // columns per MVM
-  const size_t sizes[4] = {sizeof(float) * n * kb * CH, sizeof(float) * n * kb * CH, sizeof(double) * n * d,
-                           sizeof(double) * kColBlocks * d};
+  const int kb = std::max(1, std::min((int)C, 128 / CH));  // columns per batch
+  // channels per MVM: all of a batch's, unless the blur's two lattice arrays
+  // of m x W fp32 would outgrow 160 MiB (the Infinity Cache holds 256)
+  int W = 64;
+  while (W > 4 && 2.0 * (double)L->m * W * sizeof(float) > 160.0 * (1 << 20)) W >>= 1;
+  if (W >= kb * CH) W = kb * CH;
+  const int nblk_max = (kb * CH + W - 1) / W;
+  const size_t hbytes = sizeof(float) * (size_t)n * nblk_max * W;
+  const size_t sizes[4] = {hbytes, hbytes, sizeof(double) * n * d, sizeof(double) * kColBlocks * d};
   for (int k = 0; k < 4; ++k) {
     hipError_t e = pool_alloc(&bufs[k], sizes[k], s);
     if (e != hipSuccess) {
@@ -184,17 +206,20 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
   if ((rc = launch_fill_u32((uint32_t*)dz, (size_t)n * d * 2, 0u, s))) return rc;
   for (int c0 = 0; c0 < C; c0 += kb) {
     const int nb = std::min(kb, (int)C - c0);
+    const int Wb = W == kb * CH ? nb * CH : W;  // one MVM of exactly the batch's channels
+    const int nblk = (nb * CH + Wb - 1) / Wb;
     {
       ProfScope ps(KK_GRAD, s);
-      hipLaunchKernelGGL(k_grad_channels, dim3(grid_for_g(n * nb * CH)), dim3(kBlock), 0, s, X, V, G, perm,
-                         n, d, (int)C, c0, nb, ie, H);
+      hipLaunchKernelGGL(k_grad_channels, dim3(grid_for_g(n * nblk * Wb)), dim3(kBlock), 0, s, X, V, G,
+                         perm, n, d, (int)C, c0, nb, Wb, nblk, ie, H);
       SGP_LAUNCH_CHECK("k_grad_channels");
     }
-    if ((rc = mvm_f32(L, H, nb * CH, O, s))) return rc;
+    for (int k = 0; k < nblk; ++k)
+      if ((rc = mvm_f32(L, H + (int64_t)k * n * Wb, Wb, O + (int64_t)k * n * Wb, s))) return rc;
     {
       ProfScope ps(KK_GRAD, s);
       hipLaunchKernelGGL(k_grad_accum, dim3(grid_for_g(n * d)), dim3(kBlock), 0, s, X, V, G, perm, O,
-                         n, d, (int)C, c0, nb, ie, dz);
+                         n, d, (int)C, c0, nb, Wb, ie, dz);
       SGP_LAUNCH_CHECK("k_grad_accum");
     }
   }
