@@ -254,7 +254,9 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
   int32_t dst[S::RPT];
   int nq = 0, ne = 0, q0 = 0;
   // Every load below is unconditional (indices clamped into the tile), so
-  // the whole tile is in flight at once.
+  // the whole tile is in flight at once. The tile's values and entries are
+  // read once per MVM: non-temporal, so that they do not push the partial
+  // rows, which the gather reads next, out of the caches.
   auto fetch = [&](int64_t item) {
     const int64_t t = item / a.chunks;
     const int ch = (int)(item - t * a.chunks);
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
       for (int u = 0; u < S::VPT / N; ++u) {
         const int vi = tid + u * kSplatBlock;
-        const typename Vec16<TU>::T x = src[vi < nvec ? vi : nvec - 1];
+        const typename Vec16<TU>::T x = __builtin_nontemporal_load(src + (vi < nvec ? vi : nvec - 1));
 #pragma unroll
         for (int j = 0; j < N; ++j) v[u * N + j] = x[j];
       }
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
     for (int u = 0; u < S::EPT; ++u) {
       const int e = tid + u * kSplatBlock;
-      w[u] = gw[e < ne ? e : ne - 1];
+      w[u] = __builtin_nontemporal_load(gw + (e < ne ? e : ne - 1));
     }
     // the tile starts 4-byte aligned (P is a multiple of 4) and the array
     // has spare bytes past its end
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
     for (int u = 0; u < S::EPT / 4; ++u) {
       const int wi = tid + u * kSplatBlock;
-      lp4[u] = glp4[wi < nw ? wi : nw - 1];
+      lp4[u] = __builtin_nontemporal_load(glp4 + (wi < nw ? wi : nw - 1));
     }
 #pragma unroll
     for (int u = 0; u < S::RPT; ++u) {
