@@ -102,6 +102,23 @@ __device__ __forceinline__ void write_row(T* p, const T (&v)[W]) {
   }
 }
 
+// read_row with non-temporal loads
+template <typename T, int W>
+__device__ __forceinline__ void read_row_nt(const T* p, T (&o)[W]) {
+  constexpr int N = Vec16<T>::N;
+  if constexpr (W % N == 0) {
+#pragma unroll
+    for (int i = 0; i < W / N; ++i) {
+      const typename Vec16<T>::T x = __builtin_nontemporal_load((const typename Vec16<T>::T*)(p + i * N));
+#pragma unroll
+      for (int j = 0; j < N; ++j) o[i * N + j] = x[j];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; ++i) o[i] = __builtin_nontemporal_load(p + i);
+  }
+}
+
 // write_row with non-temporal stores (streamed past the caches)
 template <typename TU, int W>
 __device__ __forceinline__ void write_row_nt(TU* p, const TU (&v)[W]) {
@@ -544,7 +561,9 @@ __global__ __launch_bounds__(kBlock) void k_splat_gather(const int32_t* __restri
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int64_t k = k0 + u < o1 ? k0 + u : o1 - 1;
-        read_row<TU, VW>(part + k * C + c, v[u]);
+        // partial rows are read once: non-temporal, which keeps the
+        // lattice values the blur reads next in the caches
+        read_row_nt<TU, VW>(part + k * C + c, v[u]);
         rv[u] = row_vert[k];
       }
 #pragma unroll
