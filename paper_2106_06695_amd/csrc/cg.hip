@@ -295,9 +295,8 @@ void defer_graph(hipGraph_t g, hipGraphExec_t e) {
   t_idle_exec = e;
 }
 
-template <int G>
-int cg_g(const sgp_lattice* L, const float* b, int C, float noise, float tol, int max_iter,
-         float* x, int32_t* iters, float* rel, hipStream_t s) {
+int cg_run(const sgp_lattice* L, const float* b, int C, float noise, float tol, int max_iter,
+           float* x, int32_t* iters, float* rel, hipStream_t s) {
   sgp_lattice* Lm = const_cast<sgp_lattice*>(L);
   const int64_t n = L->n, nC = n * C;
   int rc;
@@ -502,14 +501,5 @@ extern "C" int cg_solve(const sgp_lattice* L, const float* rhs, int32_t C, float
     set_error("cg_solve: x overlaps rhs");
     return SGP_EINVAL;
   }
-  hipStream_t s = (hipStream_t)stream;
-  switch (lanes_for(C)) {
-    case 1: return cg_g<1>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
-    case 2: return cg_g<2>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
-    case 4: return cg_g<4>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
-    case 8: return cg_g<8>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
-    case 16: return cg_g<16>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
-    case 32: return cg_g<32>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
-    default: return cg_g<64>(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, s);
-  }
+  return cg_run(L, rhs, C, noise, tol, max_iter, x, iters, rel_residual, (hipStream_t)stream);
 }

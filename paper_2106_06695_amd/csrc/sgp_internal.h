@@ -184,8 +184,8 @@ struct sgp_lattice {
   hipEvent_t last_use = nullptr;  // recorded at the end of every call on the lattice
 
   // work buffers, grown on demand
-  sgp::DevBuf ubuf;   // lattice values 4 x m x C, piece partial sums npiece x C, gather fragments
-  sgp::DevBuf cgvec;  // CG vectors x, r, p, q: 4 x n x C fp64
+  sgp::DevBuf ubuf;   // lattice values 4 x m x C (5 inside CG), piece partial sums npiece x C, gather fragments
+  sgp::DevBuf cgvec;  // CG vectors: r and p (n x C fp64 each), then x (n x C fp32)
   sgp::DevBuf cgred;  // CG partial sums and per-column scalars
 };
 
