@@ -583,13 +583,13 @@ int lattice_export(const sgp_lattice* L, int32_t* keys, int32_t* idx, float* w, 
     }
   }
   if (nbr) {
-    // device layout [direction][offset][internal point] -> [canonical point][direction][offset]
+    // device layout [direction][internal point][offset] -> [canonical point][direction][offset]
     std::vector<int32_t> tmp((size_t)D * T * m);
     SGP_HIP(hipMemcpy(tmp.data(), L->nbr.ptr, sizeof(int32_t) * tmp.size(), hipMemcpyDeviceToHost));
     for (int k = 0; k < D; ++k)
-      for (int t = 0; t < T; ++t)
-        for (int64_t ji = 0; ji < m; ++ji) {
-          const int32_t v = tmp[((size_t)k * T + t) * m + ji];
+      for (int64_t ji = 0; ji < m; ++ji)
+        for (int t = 0; t < T; ++t) {
+          const int32_t v = tmp[((size_t)k * m + ji) * T + t];
           nbr[((size_t)int2can[ji] * D + k) * T + t] = v >= 0 ? int2can[v] : -1;
         }
   }

@@ -488,18 +488,23 @@ __global__ __launch_bounds__(kBlock) void k_can2int(const int32_t* __restrict__ 
     can2int[int2can[j]] = (int32_t)j;
 }
 
-// Neighbour table in internal numbering: rows and entries both mapped.
+// Neighbour table in internal numbering: rows and entries both mapped, and
+// laid out [direction][point][offset], so that the 2r neighbours of a point
+// along one direction are adjacent (one 8-byte load for r = 1) in the blur.
+// The canonical table is [direction][offset][point].
 __global__ __launch_bounds__(kBlock) void k_nbr_internal(const int32_t* __restrict__ nbr_can,
                                                          const int32_t* __restrict__ int2can,
                                                          const int32_t* __restrict__ can2int,
-                                                         int64_t m, int64_t lists,
+                                                         int64_t m, int64_t D, int T,
                                                          int32_t* __restrict__ nbr_int) {
-  const int64_t total = lists * m;
+  const int64_t total = D * m * T;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-    const int64_t list = g / m;
-    const int64_t j = g - list * m;
-    const int32_t nb = nbr_can[list * m + int2can[j]];
+    const int64_t k = g / (m * T);
+    const int64_t rest = g - k * m * T;
+    const int64_t j = rest / T;
+    const int64_t ti = rest - j * T;
+    const int32_t nb = nbr_can[(k * T + ti) * m + int2can[j]];
     nbr_int[g] = nb >= 0 ? can2int[nb] : -1;
   }
 }
@@ -1305,7 +1310,7 @@ int build_attempt(sgp_lattice* L, const float* X, const double* f, double load_f
                        (const int32_t*)L->int2can.ptr, m, can2int);
     SGP_LAUNCH_CHECK("k_can2int");
     hipLaunchKernelGGL(k_nbr_internal, dim3(grid_for(m * D * T, kBlock, 16384)), dim3(kBlock), 0, st,
-                       nbr_can, (const int32_t*)L->int2can.ptr, can2int, m, (int64_t)D * T,
+                       nbr_can, (const int32_t*)L->int2can.ptr, can2int, m, (int64_t)D, T,
                        (int32_t*)L->nbr.ptr);
     SGP_LAUNCH_CHECK("k_nbr_internal");
   }

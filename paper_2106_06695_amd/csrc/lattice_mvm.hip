@@ -648,9 +648,10 @@ __device__ __forceinline__ void blur_rows(const TU* __restrict__ in, const int32
 #pragma unroll
   for (int i = 0; i < VW; ++i) acc[i] = 0;
   if (r == 1) {
-    // the three-tap stencil: both neighbour indices, then the three rows, in
-    // flight together
-    const int64_t lo = nb[j], hi = nb[m + j];
+    // the three-tap stencil: both neighbour indices (one 8-byte load), then
+    // the three rows, in flight together
+    const int2 lh = *(const int2*)(nb + 2 * j);
+    const int64_t lo = lh.x, hi = lh.y;
     TU v[3][VW];
     load_vw<TU, VW>(in, lo, j, C, c, vec, v[0]);
     load_vw<TU, VW>(in, j, j, C, c, vec, v[1]);
@@ -663,7 +664,7 @@ __device__ __forceinline__ void blur_rows(const TU* __restrict__ in, const int32
   }
   // neighbour rows first (2r independent loads), then the values
   int32_t nbv[2 * kMaxOrder];
-  for (int ti = 0; ti < 2 * r; ++ti) nbv[ti] = nb[(int64_t)ti * m + j];
+  for (int ti = 0; ti < 2 * r; ++ti) nbv[ti] = nb[j * (2 * r) + ti];
   int ti = 0;
   for (int t = -r; t <= r; ++t) {
     const int64_t row = t == 0 ? j : (int64_t)nbv[ti++];
@@ -779,19 +780,20 @@ __device__ __forceinline__ void blur2_rows(const TU* __restrict__ in, const int3
   // second-direction neighbours of j (t2 = -1, 0, +1), then their
   // first-direction neighbours, then the nine rows
   int64_t x[3];
-  x[0] = nb2[j];
+  const int2 lh2 = *(const int2*)(nb2 + 2 * j);
+  x[0] = lh2.x;
   x[1] = j;
-  x[2] = nb2[m + j];
+  x[2] = lh2.y;
   // (all six index loads and all nine row loads issue without waiting on
   // one another: indices of a missing x are read at j and discarded)
   int64_t y[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int64_t xa = x[a] >= 0 ? x[a] : j;
-    const int32_t lo = nb1[xa], hi = nb1[m + xa];
-    y[a][0] = x[a] >= 0 ? (int64_t)lo : -1;
+    const int2 lh1 = *(const int2*)(nb1 + 2 * xa);
+    y[a][0] = x[a] >= 0 ? (int64_t)lh1.x : -1;
     y[a][1] = x[a];
-    y[a][2] = x[a] >= 0 ? (int64_t)hi : -1;
+    y[a][2] = x[a] >= 0 ? (int64_t)lh1.y : -1;
   }
   TU v[3][3][VW];
 #pragma unroll

@@ -177,7 +177,7 @@ struct sgp_lattice {
   sgp::DevBuf row_vert;   // npiece int32: lattice point of each partial row
   sgp::DevBuf run_dst;    // npiece int32: partial row of each piece; a lattice point's
                           //   pieces occupy rows occ_ptr[j] .. occ_ptr[j+1]-1 in piece order
-  sgp::DevBuf nbr;        // (d+1) x 2r x m int32: [direction][offset][internal vertex]
+  sgp::DevBuf nbr;        // (d+1) x m x 2r int32: [direction][internal vertex][offset]
   sgp::DevBuf int2can;    // m int32: internal vertex -> canonical index
   sgp::DevBuf keys;       // m x d int32 in canonical order (first occurrence in caller's order)
 
