@@ -181,9 +181,11 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
   } guard{bufs, s};
   const int kb = std::max(1, std::min((int)C, 128 / CH));  // columns per batch
   // channels per MVM: all of a batch's, unless the blur's two lattice arrays
-  // of m x W fp32 would outgrow 160 MiB (the Infinity Cache holds 256)
+  // of m x W fp32 would outgrow 320 MiB (the Infinity Cache holds 256; a
+  // blur launch costs about the same for 8 or 16 channels, so the block is
+  // as wide as the cache allows, not narrower)
   int W = 64;
-  while (W > 4 && 2.0 * (double)L->m * W * sizeof(float) > 160.0 * (1 << 20)) W >>= 1;
+  while (W > 4 && 2.0 * (double)L->m * W * sizeof(float) > 320.0 * (1 << 20)) W >>= 1;
   if (W >= kb * CH) W = kb * CH;
   const int nblk_max = (kb * CH + W - 1) / W;
   const size_t hbytes = sizeof(float) * (size_t)n * nblk_max * W;

@@ -157,6 +157,10 @@ __device__ __forceinline__ void xcd_items(int64_t items, int64_t* first, int64_t
 // most 256 points and kMaxTileEntries entries and runs per tile).
 constexpr int kMaxTileEntries = 4096;
 constexpr int kSplatBlock = 512;   // two blocks per CU
+// The slice adds a point's entries by blocks of this many runs of its tile's
+// run list; every staged chunk of up to 16 channels holds a whole number of
+// such blocks (RC = 8 NT / G >= 512), wider chunks hold 256 or 128 rows.
+constexpr int kSliceOrderRows = 512;
 // Threads per block of k_slice_tile: 1024 (one block per CU), or for narrow
 // channel chunks just the lane groups for the 256 points of a tile (LPR =
 // G / VW lanes each), so that the lanes are not left idle. The narrow block
@@ -957,6 +961,7 @@ __global__ __launch_bounds__(NT) void k_slice_tile(
     TU* __restrict__ out, const uint32_t* __restrict__ perm, const TU* __restrict__ p,
     CgHook hook, const uint32_t* __restrict__ mperm, SliceArgs<TU> a) {
   using S = TileShape<TU, G, NT>;
+  static_assert(G > 16 || S::RC % kSliceOrderRows == 0, "staged chunks hold whole order blocks");
   extern __shared__ __align__(16) unsigned char smem[];
   TU* lu = (TU*)smem;
   float* lw = (float*)(smem + a.lds.w);
@@ -1117,19 +1122,25 @@ __global__ __launch_bounds__(NT) void k_slice_tile(
             const int eb = lp * a.D;
             // EB entries at a time: slots and weights, then their rows
             constexpr int EB = S::VW * sizeof(TU) >= 32 ? (CG ? 1 : 2) : 4;
-            // an entry outside this chunk (or past the point's d+1) reads
-            // the zero row with weight 0: fma(0, 0, acc) is acc exactly,
-            // as acc is never -0
+            // A point's entries are added by block of kSliceOrderRows runs
+            // of the tile's run list, then in vertex order, whatever RC is
+            // (a multiple of that block for chunks of up to 16 channels):
+            // the sums do not depend on the channel chunk or block shape.
+            // An entry outside the block (or past the point's d+1) reads
+            // the zero row with weight 0: fma(0, 0, acc) is acc exactly, as
+            // acc is never -0.
+            for (int s0 = 0; s0 < nr; s0 += kSliceOrderRows)
             for (int j0 = 0; j0 < a.D; j0 += EB) {
               int sv[EB];
               TU wv[EB];
 #pragma unroll
               for (int u = 0; u < EB; ++u) {
                 const int j = j0 + u < a.D ? j0 + u : a.D - 1;
-                const int sr = (int)lsl[eb + j] - r0;
+                const int sr = (int)lsl[eb + j] - r0 - s0;
                 const float wr = lw[eb + j];
-                const bool in = (unsigned)sr < (unsigned)nr && j0 + u < a.D;
-                sv[u] = in ? sr : a.lds.zrow;
+                const bool in = (unsigned)sr < (unsigned)(nr - s0 < kSliceOrderRows ? nr - s0 : kSliceOrderRows) &&
+                                j0 + u < a.D;
+                sv[u] = in ? s0 + sr : a.lds.zrow;
                 wv[u] = (TU)(in ? wr : 0.f);
               }
               TU x[EB][S::VW];

@@ -305,6 +305,36 @@ def test_cg_columns_stop_independently(sgp, orc):
     assert it1[0] == iters[0]
 
 
+def test_columns_bitwise_alone_and_batched_on_long_run_lists(sgp):
+    """Uniform 16-d points at short lengthscales (m / n(d+1) ~ 0.9): every
+    tile touches more lattice points than one staged slice chunk of a
+    16-column batch holds (512 rows), but fewer than a single column's
+    chunk. A column's MVM and CG iterates are still bitwise the same alone,
+    in a batch of 8 and in a batch of 16: the slice adds a point's entries
+    by 512-run blocks of its tile, then in vertex order, whatever the
+    chunk."""
+    _note("columns alone and batched, long run lists")
+    w = workloads.small_case(77, 20000, 16, channels=16, kind="uniform", ell_range=(0.3, 3.0))
+    lat = sgp.lattice_build(_cuda(w.X), w.lengthscales)
+    try:
+        assert lat.m > 0.8 * w.n * 17
+        y16 = sgp.lattice_mvm(lat, _cuda(w.values)).cpu().numpy()
+        x16, _, _ = sgp.cg_solve(lat, _cuda(w.values), 0.1, 0.0, max_iter=6)
+        x16 = x16.cpu().numpy()
+        y8 = sgp.lattice_mvm(lat, _cuda(w.values[:, :8])).cpu().numpy()
+        x8, _, _ = sgp.cg_solve(lat, _cuda(w.values[:, :8]), 0.1, 0.0, max_iter=6)
+        np.testing.assert_array_equal(y8, y16[:, :8])
+        np.testing.assert_array_equal(x8.cpu().numpy(), x16[:, :8])
+        for c in (0, 5, 15):
+            v1 = _cuda(w.values[:, c:c + 1])
+            y1 = sgp.lattice_mvm(lat, v1).cpu().numpy()
+            x1, _, _ = sgp.cg_solve(lat, v1, 0.1, 0.0, max_iter=6)
+            np.testing.assert_array_equal(y1[:, 0], y16[:, c])
+            np.testing.assert_array_equal(x1.cpu().numpy()[:, 0], x16[:, c])
+    finally:
+        lat.free()
+
+
 def test_cg_max_iter_reports_nonconvergence(sgp):
     w = workloads.ws1()
     lat = sgp.lattice_build(_cuda(w.X), w.lengthscales)
