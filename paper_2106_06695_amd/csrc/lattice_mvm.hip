@@ -223,6 +223,7 @@ struct SplatArgs {
   int64_t items;  // tiles x channel chunks
   int P, D, C, chunks;
   int vec_v;  // V rows of a tile are one contiguous run of 16-byte vectors
+  int vec_perm;  // V rows, reached through perm, are whole 16-byte vectors (C == G)
   int cvec;   // rows of C channels start 16-byte aligned
   double pp_scale;  // CG: factor of each tile's p . p (the noise variance)
   SplatLds lds;
@@ -296,6 +297,19 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
         for (int j = 0; j < N; ++j) v[u * N + j] = x[j];
       }
+    } else if (S::VEC && a.vec_perm) {
+      // rows in the caller's order: 16-byte vectors of one row each
+      const int nvec = np * G / N;
+#pragma unroll
+      for (int u = 0; u < S::VPT / N; ++u) {
+        const int vi = tid + u * kSplatBlock;
+        const int f = (vi < nvec ? vi : nvec - 1) * N;
+        const int64_t src = (int64_t)perm[p0 + f / G];
+        const typename Vec16<TU>::T x =
+            __builtin_nontemporal_load((const typename Vec16<TU>::T*)(V + src * a.C + f % G));
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[u * N + j] = x[j];
+      }
     } else {
 #pragma unroll
       for (int u = 0; u < S::VPT; ++u) {
@@ -344,7 +358,7 @@ __global__ __launch_bounds__(kSplatBlock) __attribute__((amdgpu_waves_per_eu(4))
   for (; item < end; item += step) {
     const int cur_nq = nq, cur_ne = ne, cur_q0 = q0;
     __syncthreads();  // the previous tile's runs are done with the LDS
-    if (S::VEC && (DIR || a.vec_v)) {
+    if (S::VEC && (DIR || a.vec_v || a.vec_perm)) {
       const int64_t p0 = (item / a.chunks) * a.P;
 #pragma unroll
       for (int u = 0; u < S::VPT / N; ++u) {
@@ -1378,6 +1392,7 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   sa.C = C;
   sa.chunks = chunks;
   sa.vec_v = (TileShape<TU, G, kSplatBlock>::VEC && !perm && C == G && aligned16(V)) ? 1 : 0;
+  sa.vec_perm = (TileShape<TU, G, kSplatBlock>::VEC && perm && C == G && aligned16(V)) ? 1 : 0;
   sa.cvec = (C % Vec16<TU>::N == 0 && aligned16(part)) ? 1 : 0;
   sa.lds = splat_lds<TU>(P, D, L->max_tile_pieces, G);
   sa.pp_scale = cgm ? (double)noise : 0.0;
