@@ -24,7 +24,7 @@
 // permutation (rows of V gathered when staged, rows of out scattered); the
 // CG solver keeps its vectors in internal order and skips it.
 //
-// Channels are processed in chunks of G (a power of two <= 64) chosen so
+// Channels are processed in chunks of G (a power of two <= 16) chosen so
 // that the staged rows fit the LDS budget; chunks are the grid's y axis.
 // Row ranges of consecutive blocks go to the same XCD (blocks are dealt
 // round-robin over the 8 XCDs), so tiles that share lattice points share
@@ -158,8 +158,8 @@ __device__ __forceinline__ void xcd_items(int64_t items, int64_t* first, int64_t
 constexpr int kMaxTileEntries = 4096;
 constexpr int kSplatBlock = 512;   // two blocks per CU
 // The slice adds a point's entries by blocks of this many runs of its tile's
-// run list; every staged chunk of up to 16 channels holds a whole number of
-// such blocks (RC = 8 NT / G >= 512), wider chunks hold 256 or 128 rows.
+// run list; every staged chunk (at most 16 channels) holds a whole number of
+// such blocks (RC = 8 NT / G >= 512).
 constexpr int kSliceOrderRows = 512;
 // Threads per block of k_slice_tile: 1024 (one block per CU), or for narrow
 // channel chunks just the lane groups for the 256 points of a tile (LPR =
@@ -975,7 +975,7 @@ __global__ __launch_bounds__(NT) void k_slice_tile(
     TU* __restrict__ out, const uint32_t* __restrict__ perm, const TU* __restrict__ p,
     CgHook hook, const uint32_t* __restrict__ mperm, SliceArgs<TU> a) {
   using S = TileShape<TU, G, NT>;
-  static_assert(G > 16 || S::RC % kSliceOrderRows == 0, "staged chunks hold whole order blocks");
+  static_assert(S::RC % kSliceOrderRows == 0, "staged chunks hold whole order blocks");
   extern __shared__ __align__(16) unsigned char smem[];
   TU* lu = (TU*)smem;
   float* lw = (float*)(smem + a.lds.w);
@@ -1138,8 +1138,8 @@ __global__ __launch_bounds__(NT) void k_slice_tile(
             constexpr int EB = S::VW * sizeof(TU) >= 32 ? (CG ? 1 : 2) : 4;
             // A point's entries are added by block of kSliceOrderRows runs
             // of the tile's run list, then in vertex order, whatever RC is
-            // (a multiple of that block for chunks of up to 16 channels):
-            // the sums do not depend on the channel chunk or block shape.
+            // (a multiple of that block): the sums do not depend on the
+            // channel chunk or block shape.
             // An entry outside the block (or past the point's d+1) reads
             // the zero row with weight 0: fma(0, 0, acc) is acc exactly, as
             // acc is never -0.
@@ -1250,9 +1250,7 @@ size_t slice_lds_g(int P, int D, int maxq, int g) {
     case 2: return slice_lds<TU, 2>(P, D, maxq).total;
     case 4: return slice_lds<TU, 4>(P, D, maxq).total;
     case 8: return slice_lds<TU, 8>(P, D, maxq).total;
-    case 16: return slice_lds<TU, 16>(P, D, maxq).total;
-    case 32: return slice_lds<TU, 32>(P, D, maxq).total;
-    default: return slice_lds<TU, 64>(P, D, maxq).total;
+    default: return slice_lds<TU, 16>(P, D, maxq).total;
   }
 }
 
@@ -1593,10 +1591,15 @@ int mvm_g(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C, TU* ou
   return SGP_OK;
 }
 
-// Channel chunk: the widest power of two <= 64 covering C for which both
-// tile kernels' LDS stages fit the budget.
+// Channel chunk: the widest power of two <= kMaxChunk covering C for which
+// both tile kernels' LDS stages fit the budget. Chunks of at most 16
+// channels stage whole blocks of kSliceOrderRows runs in the slice, so a
+// column's results are the same bit for bit whatever the chunk; more
+// columns take several chunks.
+constexpr int kMaxChunk = 16;
 int chunk_lanes(const sgp_lattice* L, int C, size_t elem) {
   int g = lanes_for(C);
+  if (g > kMaxChunk) g = kMaxChunk;
   const int D = L->d + 1, P = L->tile_points, maxq = L->max_tile_runs, maxp = L->max_tile_pieces;
   const size_t budget = (size_t)tuning().lds_budget;
   const size_t slice_budget = (size_t)tuning().slice_lds_budget;
@@ -1633,9 +1636,7 @@ int mvm_dispatch(const sgp_lattice* L, const TU* V, const uint32_t* perm, int C,
     case 2: return mvm_g<TU, 2>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
     case 4: return mvm_g<TU, 4>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
     case 8: return mvm_g<TU, 8>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
-    case 16: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
-    case 32: return mvm_g<TU, 32>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
-    default: return mvm_g<TU, 64>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
+    default: return mvm_g<TU, 16>(L, V, perm, C, out, s, noise, cgm, lc, work, up);
   }
 }
 
