@@ -641,7 +641,7 @@ template <typename TU>
 struct BlurArgs {
   const TU* in[2];
   TU* out[2];
-  const int32_t* nbr[2];  // neighbour table of this step's direction, per chain
+  const int32_t* nbr[2];  // this step's direction per chain: [point][offset], 2r per point
   int64_t m;
   int C;
   int r;
@@ -661,8 +661,8 @@ __device__ __forceinline__ void load_vw(const TU* __restrict__ in, int64_t row, 
 
 template <typename TU, int VW>
 __device__ __forceinline__ void blur_rows(const TU* __restrict__ in, const int32_t* __restrict__ nb,
-                                          int64_t m, int64_t j, int C, int c, int r, const TU* st,
-                                          bool vec, TU (&acc)[VW]) {
+                                          int64_t j, int C, int c, int r, const TU* st, bool vec,
+                                          TU (&acc)[VW]) {
 #pragma unroll
   for (int i = 0; i < VW; ++i) acc[i] = 0;
   if (r == 1) {
@@ -709,10 +709,10 @@ __global__ __launch_bounds__(kBlock) void k_blur(BlurArgs<TU> a) {
     for (int c = sub * VW; c < a.C; c += G) {
       const bool vec = a.vec && c + VW <= a.C;
       TU f[VW];
-      blur_rows<TU, VW>(a.in[0], a.nbr[0], a.m, j, a.C, c, a.r, a.st, vec, f);
+      blur_rows<TU, VW>(a.in[0], a.nbr[0], j, a.C, c, a.r, a.st, vec, f);
       if (a.chains == 2) {
         TU b[VW];
-        blur_rows<TU, VW>(a.in[1], a.nbr[1], a.m, j, a.C, c, a.r, a.st, vec, b);
+        blur_rows<TU, VW>(a.in[1], a.nbr[1], j, a.C, c, a.r, a.st, vec, b);
         if (a.sum_out) {
 #pragma unroll
           for (int i = 0; i < VW; ++i) f[i] = f[i] + b[i];
@@ -755,7 +755,7 @@ template <typename TU>
 struct Blur2Args {
   const TU* in[2];
   TU* out[2];
-  const int32_t* nbr1[2];  // first step's direction, per chain
+  const int32_t* nbr1[2];  // first step's direction, per chain ([point][offset])
   const int32_t* nbr2[2];  // second step's direction
   int64_t m;
   int C;
@@ -793,8 +793,8 @@ __device__ __forceinline__ void load_vw(const TU* __restrict__ in, int64_t row, 
 
 template <typename TU, int VW>
 __device__ __forceinline__ void blur2_rows(const TU* __restrict__ in, const int32_t* __restrict__ nb1,
-                                           const int32_t* __restrict__ nb2, int64_t m, int64_t j, int C,
-                                           int c, const TU* st, bool vec, TU (&acc)[VW]) {
+                                           const int32_t* __restrict__ nb2, int64_t j, int C, int c,
+                                           const TU* st, bool vec, TU (&acc)[VW]) {
   // second-direction neighbours of j (t2 = -1, 0, +1), then their
   // first-direction neighbours, then the nine rows
   int64_t x[3];
@@ -848,10 +848,10 @@ __global__ __launch_bounds__(kBlock) void k_blur2(Blur2Args<TU> a) {
     for (int c = sub * VW; c < a.C; c += G) {
       const bool vec = a.vec && c + VW <= a.C;
       TU f[VW];
-      blur2_rows<TU, VW>(a.in[0], a.nbr1[0], a.nbr2[0], a.m, j, a.C, c, a.st, vec, f);
+      blur2_rows<TU, VW>(a.in[0], a.nbr1[0], a.nbr2[0], j, a.C, c, a.st, vec, f);
       if (a.chains == 2) {
         TU b[VW];
-        blur2_rows<TU, VW>(a.in[1], a.nbr1[1], a.nbr2[1], a.m, j, a.C, c, a.st, vec, b);
+        blur2_rows<TU, VW>(a.in[1], a.nbr1[1], a.nbr2[1], j, a.C, c, a.st, vec, b);
         if (a.sum_out) {
 #pragma unroll
           for (int i = 0; i < VW; ++i) f[i] = f[i] + b[i];
@@ -903,7 +903,7 @@ __global__ __launch_bounds__(kBlock) void k_blur2_split(Blur2Args<TU> a) {
     for (int c = sub * VW; c < a.C; c += G) {
       const bool vec = a.vec && c + VW <= a.C;
       TU f[VW];
-      blur2_rows<TU, VW>(a.in[chain], a.nbr1[chain], a.nbr2[chain], a.m, j, a.C, c, a.st, vec, f);
+      blur2_rows<TU, VW>(a.in[chain], a.nbr1[chain], a.nbr2[chain], j, a.C, c, a.st, vec, f);
       TU* o = a.out[chain] + j * a.C + c;
       if (vec) {
         if (a.nt)

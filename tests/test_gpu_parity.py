@@ -309,10 +309,10 @@ def test_columns_bitwise_alone_and_batched_on_long_run_lists(sgp):
     """Uniform 16-d points at short lengthscales (m / n(d+1) ~ 0.9): every
     tile touches more lattice points than one staged slice chunk of a
     16-column batch holds (512 rows), but fewer than a single column's
-    chunk. A column's MVM and CG iterates are still bitwise the same alone,
-    in a batch of 8 and in a batch of 16: the slice adds a point's entries
-    by 512-run blocks of its tile, then in vertex order, whatever the
-    chunk."""
+    chunk. A column's MVM and CG iterates are still bitwise the same alone
+    and in batches of 8, 16 and 24: the slice adds a point's entries by
+    512-run blocks of its tile, then in vertex order, whatever the
+    chunk (at most 16 channels: a batch of 24 takes two)."""
     _note("columns alone and batched, long run lists")
     w = workloads.small_case(77, 20000, 16, channels=16, kind="uniform", ell_range=(0.3, 3.0))
     lat = sgp.lattice_build(_cuda(w.X), w.lengthscales)
@@ -325,6 +325,14 @@ def test_columns_bitwise_alone_and_batched_on_long_run_lists(sgp):
         x8, _, _ = sgp.cg_solve(lat, _cuda(w.values[:, :8]), 0.1, 0.0, max_iter=6)
         np.testing.assert_array_equal(y8, y16[:, :8])
         np.testing.assert_array_equal(x8.cpu().numpy(), x16[:, :8])
+        v24 = np.concatenate([w.values, w.values[:, :8]], axis=1)
+        y24 = sgp.lattice_mvm(lat, _cuda(v24)).cpu().numpy()
+        x24, _, _ = sgp.cg_solve(lat, _cuda(v24), 0.1, 0.0, max_iter=6)
+        x24 = x24.cpu().numpy()
+        np.testing.assert_array_equal(y24[:, :16], y16)
+        np.testing.assert_array_equal(y24[:, 16:], y16[:, :8])
+        np.testing.assert_array_equal(x24[:, :16], x16)
+        np.testing.assert_array_equal(x24[:, 16:], x16[:, :8])
         for c in (0, 5, 15):
             v1 = _cuda(w.values[:, c:c + 1])
             y1 = sgp.lattice_mvm(lat, v1).cpu().numpy()
