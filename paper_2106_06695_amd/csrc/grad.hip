@@ -181,9 +181,9 @@ extern "C" int lattice_mvm_grad(const sgp_lattice* L, const float* X, const floa
   } guard{bufs, s};
   const int kb = std::max(1, std::min((int)C, 128 / CH));  // columns per batch
   // channels per MVM: all of a batch's, unless the blur's two lattice arrays
-  // of m x W fp32 would outgrow 320 MiB (the Infinity Cache holds 256; a
-  // blur launch costs about the same for 8 or 16 channels, so the block is
-  // as wide as the cache allows, not narrower)
+  // of m x W fp32 would outgrow 320 MiB, a little past the 256 MiB Infinity
+  // Cache (a blur launch costs about the same for 8 as for 16 channels, so
+  // the widest block whose arrays stay near the cache's size is fastest)
   int W = 64;
   while (W > 4 && 2.0 * (double)L->m * W * sizeof(float) > 320.0 * (1 << 20)) W >>= 1;
   if (W >= kb * CH) W = kb * CH;
