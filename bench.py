@@ -139,6 +139,35 @@ def stored_traffic(stage: str):
     return sum(ks[k]["fetch_bytes"] + ks[k]["write_bytes"] for k in names)
 
 
+def hbm_probe():
+    """HBM rates a plain stream reaches on this GPU, as a reference for the
+    kernels' measured traffic: a 2 GiB fp64 device copy (read + write) and a
+    read-only sum of the same array, each the mean of 20 after 3 untimed."""
+    import torch
+    torch.cuda.set_device(0)
+    n = 256 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    copy_s = timed(lambda: b.copy_(a))
+    sum_s = timed(lambda: a.sum())
+    nbytes = n * 8
+    print(json.dumps({"hbm_probe": "2 GiB fp64: device copy (read + write) and read-only sum",
+                      "copy_GBps": 2 * nbytes / copy_s / 1e9, "read_GBps": nbytes / sum_s / 1e9,
+                      "copy_ms": copy_s * 1e3, "sum_ms": sum_s * 1e3}), flush=True)
+    return 0
+
+
 def probe():
     """A few CG iterations of the ws3 step (every MVM and CG kernel; the last
     one in its steady state), then a plain 512 MiB device copy whose
@@ -438,12 +467,16 @@ def main(argv=None):
                     help="timed steps of the ws3p secondary measurement (0 = skip)")
     ap.add_argument("--probe", action="store_true",
                     help="only run the short counter-collection workload")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only measure a plain device copy and a read-only sum (HBM reference rates)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus must be 1", file=sys.stderr)
         return 2
     if args.probe:
         return probe()
+    if args.hbm_probe:
+        return hbm_probe()
 
     import torch
     import paper_2106_06695_amd as sgp
